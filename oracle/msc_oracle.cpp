@@ -1,0 +1,637 @@
+// MSC-LBM CPU oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, obviously-correct FP64 implementation of what the
+// macroscopic-shadow-corrected lattice Boltzmann method computes on a periodic
+// lattice (D2Q9 and D3Q19).  Only tests/, the smoke check and the bench's
+// CPU-baseline leg load this library; the product path never does.  It shares
+// no code, header, table or helper with the HIP library: every formula below is
+// written out again from the paper, in the paper's order and notation.
+//
+// Paper section / equation map (the paper is the authority):
+//   lattice tables ............ App. A, Eq. (d2q9), (d3q19); cs^2 = 1/3 (Sec. 2.2.1)
+//   moments P ................. Eq. (moments)
+//   equilibrium ............... Eq. (feq), incompressible He-Luo form
+//   BDF coefficients .......... Eq. (bdf2)
+//   source moments ............ Eq. (source-moments)
+//   half-source reconstruction  Eq. (macro-reconstruct)
+//   source distribution ....... Eq. (source-distribution)
+//   TRT split / parameters .... Eq. (trt)
+//   collision ................. Eq. (collision)
+//   sweep (push streaming) .... Eq. (sweep), periodic boundary (B = I, b = 0)
+//   raw residual and RMS ...... Eq. (residual)
+//   shadow system / Schur ..... Eq. (shadow-cont), (shadow-mom), (schur)
+//   transform convention ...... Eq. (fft-convention), (wavenumbers), (shadow-mask)
+//   lift and update ........... Eq. (lift), (shadow-update)
+//   one physical step ......... Algorithm 1 (periodic shadow correction)
+//   history extrapolation and
+//   rotation order ............ Sec. 3.1, last paragraph
+//   contraction factor ........ Eq. (rho-observed)
+//
+// Readings where the paper is silent are listed in the design notes; the ones
+// that matter here: m^0 = P f^0; the extrapolation counts f^0 as an accepted
+// state; the mask is the integer test 4|j| <= N on signed indices; k in H is
+// the continuous 2*pi*j/N; nu = cs^2 (tau+ - 1/2); the BDF order inside H is
+// the current step's order.
+//
+// Build: g++ -O2 -std=c++17 -shared -fPIC msc_oracle.cpp -o liboracle.so
+// (no -ffast-math: the oracle must round like plain IEEE FP64).
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+typedef std::complex<double> cplx;
+const double kPi = 3.14159265358979323846264338327950288;
+const double cs2 = 1.0 / 3.0;  // Sec. 2.2.1
+
+// ---------------------------------------------------------------- lattices --
+// App. A: the discrete-velocity orderings fix the array layout.
+struct Lattice {
+  int d = 0, Q = 0;
+  int c[19][3];
+  double w[19];
+  int opp[19];
+};
+
+Lattice make_lattice(int d) {
+  Lattice L;
+  if (d == 2) {
+    static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static const int ob[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    L.d = 2;
+    L.Q = 9;
+    for (int k = 0; k < 9; ++k) {
+      L.c[k][0] = cx[k];
+      L.c[k][1] = cy[k];
+      L.c[k][2] = 0;
+      L.opp[k] = ob[k];
+      L.w[k] = (k == 0) ? 4.0 / 9.0 : (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+  } else if (d == 3) {
+    static const int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static const int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static const int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static const int ob[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    L.d = 3;
+    L.Q = 19;
+    for (int k = 0; k < 19; ++k) {
+      L.c[k][0] = cx[k];
+      L.c[k][1] = cy[k];
+      L.c[k][2] = cz[k];
+      L.opp[k] = ob[k];
+      L.w[k] = (k == 0) ? 1.0 / 3.0 : (k < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+  }
+  return L;
+}
+
+// ------------------------------------------------------------------- grid --
+// Canonical site order: site(x, y) = x*Ny + y in 2D, ((x*Ny)+y)*Nz + z in 3D;
+// populations are direction-major, f[k*NS + site] (the paper's global row
+// index iota(k,i,j) = (k Nx + i) Ny + j, Sec. 3.3.2, extended to 3D).
+struct Grid {
+  int d, n[3];
+  int64_t NS;
+  Grid(int d_, const int* nn) : d(d_) {
+    n[0] = nn[0];
+    n[1] = nn[1];
+    n[2] = (d_ == 3) ? nn[2] : 1;
+    NS = (int64_t)n[0] * n[1] * n[2];
+  }
+  int64_t site(int x, int y, int z) const { return ((int64_t)x * n[1] + y) * n[2] + z; }
+  void coords(int64_t s, int& x, int& y, int& z) const {
+    z = (int)(s % n[2]);
+    int64_t t = s / n[2];
+    y = (int)(t % n[1]);
+    x = (int)(t / n[1]);
+  }
+  static int wrap(int v, int N) { return ((v % N) + N) % N; }
+};
+
+// ------------------------------------------------------- sitewise algebra --
+// Eq. (moments): P f = (sum_k f_k, sum_k c_k f_k).
+void moments(const Lattice& L, const double* f, double* M) {
+  for (int a = 0; a <= L.d; ++a) M[a] = 0.0;
+  for (int k = 0; k < L.Q; ++k) {
+    M[0] += f[k];
+    for (int a = 0; a < L.d; ++a) M[1 + a] += L.c[k][a] * f[k];
+  }
+}
+
+// Eq. (feq): w_k [ p + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2) ].
+double feq_k(const Lattice& L, int k, const double* m) {
+  double cu = 0.0, uu = 0.0;
+  for (int a = 0; a < L.d; ++a) {
+    cu += L.c[k][a] * m[1 + a];
+    uu += m[1 + a] * m[1 + a];
+  }
+  return L.w[k] * (m[0] + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+}
+
+// Eq. (source-distribution):
+// Phi_k = w_k s0 + w_k [ (c_k - u)/cs2 + (c_k.u) c_k / cs2^2 ] . s_u.
+double phi_k(const Lattice& L, int k, const double* m, const double* s) {
+  double cu = 0.0;
+  for (int a = 0; a < L.d; ++a) cu += L.c[k][a] * m[1 + a];
+  double v = L.w[k] * s[0];
+  for (int a = 0; a < L.d; ++a) {
+    double coef = (L.c[k][a] - m[1 + a]) / cs2 + cu * L.c[k][a] / (cs2 * cs2);
+    v += L.w[k] * coef * s[1 + a];
+  }
+  return v;
+}
+
+// One site of the sweep's local part: reconstruct m (Eq. macro-reconstruct),
+// source s (Eq. source-moments), then the TRT collision (Eq. collision) with
+// the even/odd split of Eq. (trt).  h == nullptr means h = 0.
+void collide_site(const Lattice& L, const double* f, const double* h, double a, double wp,
+                  double wm, double* C, double* m_out, double* s_out) {
+  double M[4], m[4], s[4], hh[4] = {0, 0, 0, 0};
+  if (h)
+    for (int b = 0; b <= L.d; ++b) hh[b] = h[b];
+  moments(L, f, M);
+  for (int b = 0; b <= L.d; ++b) {
+    m[b] = (M[b] + hh[b] / 2.0) / (1.0 + a / 2.0);
+    s[b] = hh[b] - a * m[b];
+  }
+  double fe[19], ph[19];
+  for (int k = 0; k < L.Q; ++k) {
+    fe[k] = feq_k(L, k, m);
+    ph[k] = phi_k(L, k, m, s);
+  }
+  for (int k = 0; k < L.Q; ++k) {
+    int kb = L.opp[k];
+    double fp = 0.5 * (f[k] + f[kb]), fm = 0.5 * (f[k] - f[kb]);
+    double ep = 0.5 * (fe[k] + fe[kb]), em = 0.5 * (fe[k] - fe[kb]);
+    double pp = 0.5 * (ph[k] + ph[kb]), pm = 0.5 * (ph[k] - ph[kb]);
+    C[k] = f[k] - wp * (fp - ep) - wm * (fm - em) + (1.0 - wp / 2.0) * pp + (1.0 - wm / 2.0) * pm;
+  }
+  if (m_out)
+    for (int b = 0; b <= L.d; ++b) m_out[b] = m[b];
+  if (s_out)
+    for (int b = 0; b <= L.d; ++b) s_out[b] = s[b];
+}
+
+// Pairwise sum, so the FP64 RMS is not limited by a long running sum.
+double pairwise_sum(const double* v, int64_t n) {
+  if (n <= 8) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += v[i];
+    return s;
+  }
+  int64_t h = n / 2;
+  return pairwise_sum(v, h) + pairwise_sum(v + h, n - h);
+}
+
+// Complete sweep T (Eq. sweep) on a periodic domain with push streaming:
+// fT_k((x + c_k) mod N) = C_k(x).  Also returns the raw residual
+// r = T(f) - f (Eq. residual), its RMS and the conserved residual moments P r.
+void sweep(const Lattice& L, const Grid& G, const double* f, const double* h, double a,
+           double wp, double wm, double* fT, double* Pr, double* R) {
+  const int Q = L.Q, D = L.d;
+  const int64_t NS = G.NS;
+  std::vector<double> fs(Q), C(Q), hs(D + 1);
+  for (int64_t s = 0; s < NS; ++s) {
+    for (int k = 0; k < Q; ++k) fs[k] = f[k * NS + s];
+    if (h)
+      for (int b = 0; b <= D; ++b) hs[b] = h[b * NS + s];
+    collide_site(L, fs.data(), h ? hs.data() : nullptr, a, wp, wm, C.data(), nullptr, nullptr);
+    int x, y, z;
+    G.coords(s, x, y, z);
+    for (int k = 0; k < Q; ++k) {
+      int xd = Grid::wrap(x + L.c[k][0], G.n[0]);
+      int yd = Grid::wrap(y + L.c[k][1], G.n[1]);
+      int zd = (D == 3) ? Grid::wrap(z + L.c[k][2], G.n[2]) : 0;
+      fT[k * NS + G.site(xd, yd, zd)] = C[k];
+    }
+  }
+  std::vector<double> r2((size_t)Q * NS);
+  for (int64_t s = 0; s < NS; ++s) {
+    double pr[4] = {0, 0, 0, 0};
+    for (int k = 0; k < Q; ++k) {
+      double r = fT[k * NS + s] - f[k * NS + s];
+      r2[(size_t)k * NS + s] = r * r;
+      pr[0] += r;
+      for (int b = 0; b < D; ++b) pr[1 + b] += L.c[k][b] * r;
+    }
+    if (Pr)
+      for (int b = 0; b <= D; ++b) Pr[b * NS + s] = pr[b];
+  }
+  if (R) *R = std::sqrt(pairwise_sum(r2.data(), (int64_t)Q * NS) / ((double)Q * NS));
+}
+
+// --------------------------------------------------------------- transforms --
+// Textbook iterative radix-2 Cooley-Tukey FFT of one line (length a power of
+// two).  tw[t] = exp(sign * 2 pi i t / n), t < n/2, is the twiddle table of the
+// line length.  sign = -1: forward, unnormalised; sign = +1: inverse without
+// the 1/N factor (applied by the caller), Eq. (fft-convention).
+void fft_line(std::vector<cplx>& v, const std::vector<cplx>& tw) {
+  const size_t n = v.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(v[i], v[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    const size_t step = n / len;
+    for (size_t i = 0; i < n; i += len) {
+      for (size_t t = 0; t < len / 2; ++t) {
+        cplx u = v[i + t], x = v[i + t + len / 2] * tw[t * step];
+        v[i + t] = u + x;
+        v[i + t + len / 2] = u - x;
+      }
+    }
+  }
+}
+
+std::vector<cplx> twiddles(size_t n, int sign) {
+  std::vector<cplx> tw(n / 2 + 1);
+  for (size_t t = 0; t < tw.size(); ++t) {
+    double ang = sign * 2.0 * kPi * (double)t / (double)n;
+    tw[t] = cplx(std::cos(ang), std::sin(ang));
+  }
+  return tw;
+}
+
+// Multi-dimensional transform of one field in canonical order, dimension by
+// dimension.  Inverse includes 1/N_Omega (Eq. fft-convention).
+void fft_nd(const Grid& G, std::vector<cplx>& g, int sign) {
+  const int D = G.d;
+  for (int ax = 0; ax < D; ++ax) {
+    int Nax = G.n[ax];
+    std::vector<cplx> line(Nax);
+    std::vector<cplx> tw = twiddles(Nax, sign);
+    for (int64_t s = 0; s < G.NS; ++s) {
+      int c[3];
+      G.coords(s, c[0], c[1], c[2]);
+      if (c[ax] != 0) continue;  // one line per start point with coordinate 0 on ax
+      for (int i = 0; i < Nax; ++i) {
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[ax] = i;
+        line[i] = g[G.site(cc[0], cc[1], cc[2])];
+      }
+      fft_line(line, tw);
+      for (int i = 0; i < Nax; ++i) {
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[ax] = i;
+        g[G.site(cc[0], cc[1], cc[2])] = line[i];
+      }
+    }
+  }
+  if (sign > 0) {
+    double inv = 1.0 / (double)G.NS;
+    for (auto& z : g) z *= inv;
+  }
+}
+
+// Eq. (wavenumbers): signed index j for 0 <= j <= N/2, j - N above.
+int signed_index(int j, int N) { return (j <= N / 2) ? j : j - N; }
+
+// Eq. (shadow-mask): keep |k_alpha| <= pi/2, boundary retained; evaluated as
+// the integer test 4|j_alpha| <= N so that no float comparison decides it.
+bool in_mask(int sj, int N) { return 4 * std::abs(sj) <= N; }
+
+// Periodic macroscopic shadow correction field (Eq. shadow-update up to the
+// lift): dm = F^{-1}[ chi H^{-1} F[P r] ].  Pr and dm hold (d+1) fields.
+void shadow_field(const Grid& G, const double* Pr, double a, double nu, double* dm) {
+  const int D = G.d;
+  const int64_t NS = G.NS;
+  std::vector<std::vector<cplx>> rh(D + 1, std::vector<cplx>(NS));
+  for (int b = 0; b <= D; ++b) {
+    for (int64_t s = 0; s < NS; ++s) rh[b][s] = cplx(Pr[b * NS + s], 0.0);
+    fft_nd(G, rh[b], -1);
+  }
+  std::vector<std::vector<cplx>> sol(D + 1, std::vector<cplx>(NS, cplx(0.0, 0.0)));
+  const cplx I(0.0, 1.0);
+  for (int64_t s = 0; s < NS; ++s) {
+    int c[3];
+    G.coords(s, c[0], c[1], c[2]);
+    bool keep = true;
+    double k[3] = {0, 0, 0}, kk = 0.0;
+    for (int ax = 0; ax < D; ++ax) {
+      int sj = signed_index(c[ax], G.n[ax]);
+      if (!in_mask(sj, G.n[ax])) keep = false;
+      k[ax] = 2.0 * kPi * sj / G.n[ax];
+      kk += k[ax] * k[ax];
+    }
+    if (!keep) continue;
+    // Eq. (schur): block elimination of H(k) = [[a, i k^T], [cs2 i k, (a + nu|k|^2) I]].
+    double bcoef = a + nu * kk;
+    cplx kdotr(0.0, 0.0);
+    for (int ax = 0; ax < D; ++ax) kdotr += k[ax] * rh[1 + ax][s];
+    cplx dp = (rh[0][s] - I * kdotr / bcoef) / (a + cs2 * kk / bcoef);
+    sol[0][s] = dp;
+    for (int ax = 0; ax < D; ++ax) sol[1 + ax][s] = (rh[1 + ax][s] - cs2 * I * k[ax] * dp) / bcoef;
+  }
+  for (int b = 0; b <= D; ++b) {
+    fft_nd(G, sol[b], +1);
+    for (int64_t s = 0; s < NS; ++s) dm[b * NS + s] = sol[b][s].real();
+  }
+}
+
+// Eq. (lift) and Eq. (shadow-update): f <- fT + E dm,
+// E dm = w_k (dp + c_k . du / cs2).
+void lift_add(const Lattice& L, const Grid& G, const double* fT, const double* dm, double* f) {
+  const int64_t NS = G.NS;
+  for (int64_t s = 0; s < NS; ++s)
+    for (int k = 0; k < L.Q; ++k) {
+      double cu = 0.0;
+      for (int a = 0; a < L.d; ++a) cu += L.c[k][a] * dm[(1 + a) * NS + s];
+      f[k * NS + s] = fT[k * NS + s] + L.w[k] * (dm[s] + cu / cs2);
+    }
+}
+
+// Eq. (macro-reconstruct) over the field: m = (P f + h/2)/(1 + a/2).
+void reconstruct(const Lattice& L, const Grid& G, const double* f, const double* h, double a,
+                 double* m) {
+  const int64_t NS = G.NS;
+  std::vector<double> fs(L.Q);
+  double M[4];
+  for (int64_t s = 0; s < NS; ++s) {
+    for (int k = 0; k < L.Q; ++k) fs[k] = f[k * NS + s];
+    moments(L, fs.data(), M);
+    for (int b = 0; b <= L.d; ++b) m[b * NS + s] = (M[b] + (h ? h[b * NS + s] : 0.0) / 2.0) / (1.0 + a / 2.0);
+  }
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+// =============================================================== C ABI ====
+extern "C" {
+
+struct orc_params {
+  int d;            // 2 or 3
+  int n[3];         // grid extents
+  double tau_plus;  // Eq. (trt)
+  double tau_minus;
+  double dt;        // physical BDF step
+  double eps;       // raw-residual tolerance
+  int kmax;         // inner cap
+  int nmin;         // minimum accepted inner count
+  int corrector;    // 0 = plain Picard, 1 = periodic shadow correction
+};
+
+struct orc_step_stats {
+  int q;
+  int iters;
+  double R_first;
+  double R_final;
+  double rho_obs;  // NaN when fewer than three residuals (Eq. rho-observed)
+  int converged;
+};
+
+// status codes mirror the library's meaning
+enum { ORC_OK = 0, ORC_ERR_INVALID = 1, ORC_ERR_NONCONVERGED = 5, ORC_ERR_NONFINITE = 6 };
+
+int orc_lattice(int d, int* Q, int* c, double* w, int* opp) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  *Q = L.Q;
+  for (int k = 0; k < L.Q; ++k) {
+    for (int a = 0; a < 3; ++a) c[3 * k + a] = L.c[k][a];
+    w[k] = L.w[k];
+    opp[k] = L.opp[k];
+  }
+  return ORC_OK;
+}
+
+void orc_feq_site(int d, const double* m, double* feq) {
+  Lattice L = make_lattice(d);
+  for (int k = 0; k < L.Q; ++k) feq[k] = feq_k(L, k, m);
+}
+
+void orc_phi_site(int d, const double* m, const double* s, double* phi) {
+  Lattice L = make_lattice(d);
+  for (int k = 0; k < L.Q; ++k) phi[k] = phi_k(L, k, m, s);
+}
+
+void orc_collide_site(int d, const double* f, const double* h, double a, double wp, double wm,
+                      double* C, double* m, double* s) {
+  Lattice L = make_lattice(d);
+  collide_site(L, f, h, a, wp, wm, C, m, s);
+}
+
+// One evaluation of T (Eq. sweep) with residual (Eq. residual).  h may be NULL.
+int orc_sweep(int d, const int* n, const double* f, const double* h, double a, double wp,
+              double wm, double* fT, double* Pr, double* R) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  sweep(L, G, f, h, a, wp, wm, fT, Pr, R);
+  return ORC_OK;
+}
+
+// Shadow correction field dm from residual moments (Eq. shadow-update).
+int orc_shadow(int d, const int* n, const double* Pr, double a, double nu, double* dm) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Grid G(d, n);
+  shadow_field(G, Pr, a, nu, dm);
+  return ORC_OK;
+}
+
+// One corrected iteration: fT = T(f); r; dm; f_next = fT + E dm.
+int orc_corrected_iteration(int d, const int* n, const double* f, const double* h, double a,
+                            double wp, double wm, double nu, double* f_next, double* fT,
+                            double* Pr, double* dm, double* R) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  sweep(L, G, f, h, a, wp, wm, fT, Pr, R);
+  shadow_field(G, Pr, a, nu, dm);
+  lift_add(L, G, fT, dm, f_next);
+  return ORC_OK;
+}
+
+// Multi-dimensional complex transform (own radix-2), in place.
+int orc_fft(int d, const int* n, double* re, double* im, int inverse) {
+  Grid G(d, n);
+  std::vector<cplx> g(G.NS);
+  for (int64_t s = 0; s < G.NS; ++s) g[s] = cplx(re[s], im[s]);
+  fft_nd(G, g, inverse ? +1 : -1);
+  for (int64_t s = 0; s < G.NS; ++s) {
+    re[s] = g[s].real();
+    im[s] = g[s].imag();
+  }
+  return ORC_OK;
+}
+
+// Canonical tables for the bit-exact comparison: neighbour index of
+// (x + c_k) mod N, signed wavenumber index per axis, and the mask chi.
+int orc_tables(int d, const int* n, int32_t* nbr, int32_t* signed_idx, uint8_t* mask) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  for (int64_t s = 0; s < G.NS; ++s) {
+    int x, y, z;
+    G.coords(s, x, y, z);
+    for (int k = 0; k < L.Q; ++k) {
+      int xd = Grid::wrap(x + L.c[k][0], G.n[0]);
+      int yd = Grid::wrap(y + L.c[k][1], G.n[1]);
+      int zd = (d == 3) ? Grid::wrap(z + L.c[k][2], G.n[2]) : 0;
+      nbr[k * G.NS + s] = (int32_t)G.site(xd, yd, zd);
+    }
+  }
+  int off = 0;
+  for (int ax = 0; ax < d; ++ax)
+    for (int j = 0; j < G.n[ax]; ++j) signed_idx[off++] = signed_index(j, G.n[ax]);
+  for (int64_t s = 0; s < G.NS; ++s) {
+    int c[3];
+    G.coords(s, c[0], c[1], c[2]);
+    bool keep = true;
+    for (int ax = 0; ax < d; ++ax) keep = keep && in_mask(signed_index(c[ax], G.n[ax]), G.n[ax]);
+    mask[s] = keep ? 1 : 0;
+  }
+  return ORC_OK;
+}
+
+// Initial state: f^0 = feq(p0, u0) sitewise (Sec. 4.1).
+int orc_init_populations(int d, const int* n, const double* p0, const double* u0, double* f) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  for (int64_t s = 0; s < G.NS; ++s) {
+    double m[4];
+    m[0] = p0[s];
+    for (int a = 0; a < d; ++a) m[1 + a] = u0[a * G.NS + s];
+    for (int k = 0; k < L.Q; ++k) f[k * G.NS + s] = feq_k(L, k, m);
+  }
+  return ORC_OK;
+}
+
+// Field of moments P f (no source): (d+1) x NS.
+int orc_moments(int d, const int* n, const double* f, double* M) {
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  reconstruct(L, G, f, nullptr, 0.0, M);
+  return ORC_OK;
+}
+
+// Explicit march: f <- S C(f; a = 0, h = 0), nsteps lattice steps.
+int orc_explicit(int d, const int* n, double wp, double wm, double* f, int64_t nsteps) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  std::vector<double> tmp((size_t)L.Q * G.NS);
+  for (int64_t t = 0; t < nsteps; ++t) {
+    sweep(L, G, f, nullptr, 0.0, wp, wm, tmp.data(), nullptr, nullptr);
+    std::memcpy(f, tmp.data(), sizeof(double) * tmp.size());
+  }
+  return ORC_OK;
+}
+
+// Dual-time BDF march by Algorithm 1 (corrector = 1) or plain Picard
+// (corrector = 0), nsteps physical steps from (p0, u0).
+//   schedule: NULL for tolerance stopping; otherwise schedule[i] is the inner
+//             count at which step i is accepted (replay of a recorded run).
+//   stats:    nsteps records (may be NULL).
+//   Rhist:    optional nsteps*kmax residual histories (may be NULL).
+//   f_out:    Q*NS populations f^n after the march; m_out: (d+1)*NS, m^n.
+// On failure the outputs hold the last accepted state and *steps_done tells
+// how many steps were accepted.
+int orc_march(const orc_params* P, const double* p0, const double* u0, int nsteps,
+              const int* schedule, orc_step_stats* stats, double* Rhist, double* f_out,
+              double* m_out, int* steps_done) {
+  const int d = P->d;
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, P->n);
+  const int Q = L.Q, D = d;
+  const int64_t NS = G.NS;
+  const size_t FQ = (size_t)Q * NS, FM = (size_t)(D + 1) * NS;
+  const double wp = 1.0 / P->tau_plus, wm = 1.0 / P->tau_minus;
+  const double nu = cs2 * (P->tau_plus - 0.5);  // Eq. (trt)
+  const int mcap = (d == 2) ? 10 : 8;           // Eq. (rho-observed) window
+
+  // f^n, f^{n-1}, f^{n-2}; m^n, m^{n-1}
+  std::vector<double> fn(FQ), fn1(FQ), fn2(FQ), mn(FM), mn1(FM);
+  orc_init_populations(d, P->n, p0, u0, fn.data());
+  reconstruct(L, G, fn.data(), nullptr, 0.0, mn.data());  // m^0 = P f^0
+  mn1 = mn;
+  std::vector<double> f(FQ), fT(FQ), Pr(FM), dm(FM), h(FM), mnew(FM);
+  std::vector<double> Rl;
+  int status = ORC_OK, done = 0;
+  for (int step = 0; step < nsteps; ++step) {
+    // Eq. (bdf2): BDF1 on the first physical step, BDF2 afterwards.
+    const int q = (step == 0) ? 1 : 2;
+    const double a = (q == 1) ? 1.0 / P->dt : 3.0 / (2.0 * P->dt);
+    for (size_t i = 0; i < FM; ++i)
+      h[i] = (q == 1) ? mn[i] / P->dt : (4.0 * mn[i] - mn1[i]) / (2.0 * P->dt);
+    // Initial trial by population-history extrapolation (Sec. 3.1).
+    for (size_t i = 0; i < FQ; ++i) {
+      if (step == 0)
+        f[i] = fn[i];
+      else if (step == 1)
+        f[i] = 2.0 * fn[i] - fn1[i];
+      else
+        f[i] = 3.0 * fn[i] - 3.0 * fn1[i] + fn2[i];
+    }
+    Rl.clear();
+    bool accepted = false;
+    for (int ell = 1; ell <= P->kmax; ++ell) {
+      double R;
+      sweep(L, G, f.data(), h.data(), a, wp, wm, fT.data(), Pr.data(), &R);
+      Rl.push_back(R);
+      if (Rhist) Rhist[(size_t)step * P->kmax + (ell - 1)] = R;
+      bool pass = schedule ? (ell == schedule[step])
+                           : (ell >= P->nmin && is_fin(R) && R < P->eps);
+      if (pass) {
+        // accept: m^{n+1} = R(fT) with the unchanged histories, then rotate.
+        reconstruct(L, G, fT.data(), h.data(), a, mnew.data());
+        fn2.swap(fn1);
+        fn1.swap(fn);
+        fn = fT;
+        mn1.swap(mn);
+        mn = mnew;
+        accepted = true;
+        break;
+      }
+      if (!is_fin(R)) {
+        status = ORC_ERR_NONFINITE;
+        break;
+      }
+      if (ell == P->kmax) break;
+      if (P->corrector == 1) {
+        shadow_field(G, Pr.data(), a, nu, dm.data());
+        lift_add(L, G, fT.data(), dm.data(), f.data());
+      } else {
+        f.swap(fT);
+      }
+    }
+    if (stats) {
+      orc_step_stats& st = stats[step];
+      st.q = q;
+      st.iters = (int)Rl.size();
+      st.R_first = Rl.empty() ? NAN : Rl.front();
+      st.R_final = Rl.empty() ? NAN : Rl.back();
+      int lf = (int)Rl.size();
+      if (lf >= 3) {
+        int mr = std::min(mcap, lf - 1);
+        double acc = 0.0;
+        for (int j = lf - mr + 1; j <= lf; ++j) acc += std::log(Rl[j - 1] / Rl[j - 2]);
+        st.rho_obs = std::exp(acc / mr);
+      } else {
+        st.rho_obs = NAN;
+      }
+      st.converged = accepted ? 1 : 0;
+    }
+    if (!accepted) {
+      if (status == ORC_OK) status = ORC_ERR_NONCONVERGED;
+      break;
+    }
+    ++done;
+  }
+  if (f_out) std::memcpy(f_out, fn.data(), sizeof(double) * FQ);
+  if (m_out) std::memcpy(m_out, mn.data(), sizeof(double) * FM);
+  if (steps_done) *steps_done = done;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+"""Python binding of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the bench's CPU-baseline leg import this
+module.  It wraps ``liboracle.so`` (built from ``msc_oracle.cpp`` by
+``build()`` below) with numpy arrays in the canonical layout: populations are
+direction-major ``f[k, x, y(, z)]`` and moment fields ``m[b, x, y(, z)]`` with
+``b = 0`` the pressure-like variable and ``b = 1..d`` the velocity (Eq.
+(moments), Eq. (unknowns) of the paper).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "msc_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain g++ (no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("tau_plus", ctypes.c_double),
+        ("tau_minus", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("kmax", ctypes.c_int),
+        ("nmin", ctypes.c_int),
+        ("corrector", ctypes.c_int),
+    ]
+
+
+class OrcStepStats(ctypes.Structure):
+    _fields_ = [
+        ("q", ctypes.c_int),
+        ("iters", ctypes.c_int),
+        ("R_first", ctypes.c_double),
+        ("R_final", ctypes.c_double),
+        ("rho_obs", ctypes.c_double),
+        ("converged", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.orc_lattice.argtypes = [ctypes.c_int, _ip, _ip, _dp, _ip]
+        L.orc_feq_site.argtypes = [ctypes.c_int, _dp, _dp]
+        L.orc_phi_site.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.orc_collide_site.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _dp, _dp, _dp]
+        L.orc_sweep.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, _dp, _dp, _dp]
+        L.orc_shadow.argtypes = [ctypes.c_int, _ip, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_corrected_iteration.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              _dp, _dp, _dp, _dp, _dp]
+        L.orc_fft.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_int]
+        L.orc_tables.argtypes = [ctypes.c_int, _ip, _ip, _ip, ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_init_populations.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp]
+        L.orc_moments.argtypes = [ctypes.c_int, _ip, _dp, _dp]
+        L.orc_explicit.argtypes = [ctypes.c_int, _ip, ctypes.c_double, ctypes.c_double, _dp,
+                                   ctypes.c_int64]
+        L.orc_march.argtypes = [ctypes.POINTER(OrcParams), _dp, _dp, ctypes.c_int, _ip,
+                                ctypes.POINTER(OrcStepStats), _dp, _dp, _dp, _ip]
+        for name in ("orc_lattice", "orc_sweep", "orc_shadow", "orc_corrected_iteration", "orc_fft",
+                     "orc_tables", "orc_init_populations", "orc_moments", "orc_explicit",
+                     "orc_march"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dims(shape_n):
+    n = list(shape_n) + [1] * (3 - len(shape_n))
+    return (ctypes.c_int32 * 3)(*n)
+
+
+# ------------------------------------------------------------------ lattice --
+def lattice(d: int):
+    """(c[Q,3] int, w[Q], opp[Q]) from App. A."""
+    Q = ctypes.c_int32()
+    c = np.zeros(19 * 3, dtype=np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, dtype=np.int32)
+    rc = lib().orc_lattice(d, ctypes.byref(Q), c.ctypes.data_as(_ip), _p(w), opp.ctypes.data_as(_ip))
+    assert rc == 0
+    q = Q.value
+    return c[: 3 * q].reshape(q, 3).copy(), w[:q].copy(), opp[:q].copy()
+
+
+def feq_site(d, m):
+    m = _c64(m)
+    _, w, _ = lattice(d)
+    out = np.zeros(len(w))
+    lib().orc_feq_site(d, _p(m), _p(out))
+    return out
+
+
+def phi_site(d, m, s):
+    m, s = _c64(m), _c64(s)
+    _, w, _ = lattice(d)
+    out = np.zeros(len(w))
+    lib().orc_phi_site(d, _p(m), _p(s), _p(out))
+    return out
+
+
+def collide_site(d, f, h, a, wp, wm):
+    f = _c64(f)
+    Q = f.shape[0]
+    C = np.zeros(Q)
+    m = np.zeros(d + 1)
+    s = np.zeros(d + 1)
+    hh = _c64(h) if h is not None else None
+    lib().orc_collide_site(d, _p(f), _p(hh) if hh is not None else None, a, wp, wm, _p(C), _p(m),
+                           _p(s))
+    return C, m, s
+
+
+# ---------------------------------------------------------------- operators --
+def sweep(f, h, a, wp, wm):
+    """One evaluation of T: returns (fT, Pr, R)."""
+    f = _c64(f)
+    Q = f.shape[0]
+    d = f.ndim - 1
+    n = _dims(f.shape[1:])
+    fT = np.zeros_like(f)
+    Pr = np.zeros((d + 1,) + f.shape[1:])
+    R = ctypes.c_double()
+    hh = _c64(h) if h is not None else None
+    rc = lib().orc_sweep(d, n, _p(f), _p(hh) if hh is not None else None, a, wp, wm, _p(fT), _p(Pr),
+                         ctypes.byref(R))
+    assert rc == 0 and Q in (9, 19)
+    return fT, Pr, R.value
+
+
+def shadow(Pr, a, nu):
+    Pr = _c64(Pr)
+    d = Pr.ndim - 1
+    dm = np.zeros_like(Pr)
+    rc = lib().orc_shadow(d, _dims(Pr.shape[1:]), _p(Pr), a, nu, _p(dm))
+    assert rc == 0
+    return dm
+
+
+def corrected_iteration(f, h, a, wp, wm, nu):
+    """fT = T(f); dm from P r; returns (f_next, fT, Pr, dm, R)."""
+    f = _c64(f)
+    d = f.ndim - 1
+    fn = np.zeros_like(f)
+    fT = np.zeros_like(f)
+    Pr = np.zeros((d + 1,) + f.shape[1:])
+    dm = np.zeros_like(Pr)
+    R = ctypes.c_double()
+    hh = _c64(h) if h is not None else None
+    rc = lib().orc_corrected_iteration(d, _dims(f.shape[1:]), _p(f),
+                                       _p(hh) if hh is not None else None, a, wp, wm, nu, _p(fn),
+                                       _p(fT), _p(Pr), _p(dm), ctypes.byref(R))
+    assert rc == 0
+    return fn, fT, Pr, dm, R.value
+
+
+def fft(z, inverse=False):
+    z = np.asarray(z, dtype=np.complex128)
+    re = np.ascontiguousarray(z.real)
+    im = np.ascontiguousarray(z.imag)
+    rc = lib().orc_fft(z.ndim, _dims(z.shape), _p(re), _p(im), 1 if inverse else 0)
+    assert rc == 0
+    return re + 1j * im
+
+
+def tables(d, shape):
+    """(nbr[Q, NS] int32, signed index per axis (concatenated), mask[NS] uint8)."""
+    Q = 9 if d == 2 else 19
+    NS = int(np.prod(shape))
+    nbr = np.zeros(Q * NS, dtype=np.int32)
+    sidx = np.zeros(int(sum(shape)), dtype=np.int32)
+    mask = np.zeros(NS, dtype=np.uint8)
+    rc = lib().orc_tables(d, _dims(shape), nbr.ctypes.data_as(_ip), sidx.ctypes.data_as(_ip),
+                          mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    assert rc == 0
+    return nbr.reshape(Q, NS), sidx, mask
+
+
+def init_populations(p0, u0):
+    p0, u0 = _c64(p0), _c64(u0)
+    d = u0.shape[0]
+    Q = 9 if d == 2 else 19
+    f = np.zeros((Q,) + p0.shape)
+    rc = lib().orc_init_populations(d, _dims(p0.shape), _p(p0), _p(u0), _p(f))
+    assert rc == 0
+    return f
+
+
+def moments(f):
+    f = _c64(f)
+    d = f.ndim - 1
+    M = np.zeros((d + 1,) + f.shape[1:])
+    lib().orc_moments(d, _dims(f.shape[1:]), _p(f), _p(M))
+    return M
+
+
+def explicit(f, nsteps, wp=1.0, wm=1.0):
+    f = _c64(f).copy()
+    d = f.ndim - 1
+    rc = lib().orc_explicit(d, _dims(f.shape[1:]), wp, wm, _p(f), int(nsteps))
+    assert rc == 0
+    return f
+
+
+@dataclass
+class MarchResult:
+    status: int
+    steps_done: int
+    f: np.ndarray
+    m: np.ndarray
+    stats: list
+    Rhist: np.ndarray | None
+
+
+def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_plus=1.0,
+          tau_minus=1.0, schedule=None, keep_rhist=False) -> MarchResult:
+    """Dual-time march by Algorithm 1 (corrector=1) or Picard (corrector=0)."""
+    p0, u0 = _c64(p0), _c64(u0)
+    d = u0.shape[0]
+    shape = p0.shape
+    Q = 9 if d == 2 else 19
+    P = OrcParams()
+    P.d = d
+    P.n = (ctypes.c_int * 3)(*(list(shape) + [1] * (3 - len(shape))))
+    P.tau_plus, P.tau_minus, P.dt, P.eps = tau_plus, tau_minus, dt, eps
+    P.kmax, P.nmin, P.corrector = kmax, nmin, corrector
+    st = (OrcStepStats * max(nsteps, 1))()
+    f = np.zeros((Q,) + shape)
+    m = np.zeros((d + 1,) + shape)
+    sched = None
+    if schedule is not None:
+        sched = np.ascontiguousarray(schedule, dtype=np.int32)
+    Rh = np.full(nsteps * kmax, np.nan) if keep_rhist else None
+    done = ctypes.c_int32()
+    rc = lib().orc_march(ctypes.byref(P), _p(p0), _p(u0), nsteps,
+                         sched.ctypes.data_as(_ip) if sched is not None else None, st,
+                         _p(Rh) if Rh is not None else None, _p(f), _p(m), ctypes.byref(done))
+    stats = [dict(q=s.q, iters=s.iters, R_first=s.R_first, R_final=s.R_final, rho_obs=s.rho_obs,
+                  converged=s.converged) for s in st[: nsteps]]
+    return MarchResult(rc, done.value, f, m, stats,
+                       Rh.reshape(nsteps, kmax) if Rh is not None else None)
