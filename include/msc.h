@@ -1,0 +1,219 @@
+/*
+ * msc.h -- C ABI of the MI355X (gfx950) MSC-LBM library.
+ *
+ * The library advances the fully discrete lattice Boltzmann population
+ * equation on a periodic D2Q9 or D3Q19 lattice by BDF dual-time stepping,
+ * where every physical step solves the population fixed point
+ * T_{q,h_q}(f) = f (paper Sec. 2.1, Eq. fixed-point-problem) with the
+ * macroscopic-shadow-corrected inner iteration of Algorithm 1, and also runs
+ * the explicit collide-stream march that uses the same sweep kernel
+ * (Sec. 4.1, last paragraph).
+ *
+ * Conventions shared by every entry point
+ *  - All calls return msc_status; MSC_OK is 0.  No C++ exception crosses this
+ *    interface.
+ *  - Field layout is the canonical site order: site(x, y) = x*Ny + y in 2D and
+ *    ((x*Ny) + y)*Nz + z in 3D (last index fastest).  Population arrays are
+ *    direction-major, f[k*N_sites + site], with the direction ordering of
+ *    App. A (Eq. d2q9, d3q19).  Hydrodynamic fields m = (p_hat, u_1..u_d) are
+ *    stored as m[b*N_sites + site], b = 0 the pressure-like variable.
+ *  - Host arrays are FP64 regardless of the storage precision the context
+ *    computes in; they are converted at the boundary.  With
+ *    params.inputs_on_device set, msc_init's initial fields and
+ *    msc_moments's outputs are device pointers instead.
+ *  - All device work is ordered on params.stream (a hipStream_t, or NULL for
+ *    a stream the context creates).  Calls that return host-visible data
+ *    synchronise that stream.
+ *  - A context is not thread-safe; separate contexts are independent.
+ *  - After a HIP runtime error the context is unusable: every later call
+ *    returns MSC_ERR_STATE until msc_free.
+ *  - Nothing here allocates on the host side on behalf of the caller; all
+ *    buffers passed in are owned by the caller and only read or written for
+ *    the duration of the call.
+ */
+#ifndef MSC_H_
+#define MSC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum msc_status {
+  MSC_OK = 0,
+  MSC_ERR_INVALID_ARG = 1,   /* a parameter or size outside the supported range */
+  MSC_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+  MSC_ERR_DEVICE = 3,        /* a HIP runtime call failed (context now unusable) */
+  MSC_ERR_STATE = 4,         /* context unusable after an earlier device error */
+  MSC_ERR_NONCONVERGED = 5,  /* K_max inner iterations without acceptance (Alg. 1, last line) */
+  MSC_ERR_NONFINITE = 6,     /* a non-finite raw residual (never accepted, Sec. 4.1) */
+  MSC_ERR_UNSUPPORTED = 7    /* valid request this build does not implement */
+} msc_status;
+
+typedef enum msc_lattice { MSC_D2Q9 = 2, MSC_D3Q19 = 3 } msc_lattice;
+
+typedef enum msc_corrector {
+  MSC_CORRECTOR_PICARD = 0, /* plain fixed-point iteration f <- T(f) */
+  MSC_CORRECTOR_SHADOW = 1  /* periodic macroscopic shadow correction (Alg. 1) */
+} msc_corrector;
+
+typedef enum msc_storage {
+  MSC_STORAGE_FP64 = 0, /* FP64 populations, FP64 arithmetic */
+  MSC_STORAGE_FP32 = 1, /* FP32 populations and arithmetic; FP64 BDF history
+                           combination, residual reductions and per-wavevector solve */
+  MSC_STORAGE_FP16_DEV = 2 /* FP16 deviation from equilibrium plus FP32 moments */
+} msc_storage;
+
+typedef struct msc_params {
+  int32_t lattice;   /* msc_lattice */
+  int32_t n[3];      /* extents (x, y, z); powers of two >= 4; n[2] ignored in 2D */
+  double tau_plus;   /* TRT relaxation times (Eq. trt); both > 1/2.  nu = (tau_plus - 1/2)/3 */
+  double tau_minus;
+  double dt;         /* physical BDF step, > 0, in lattice time units */
+  double eps;        /* raw-residual RMS acceptance tolerance, > 0 (Eq. residual) */
+  int32_t k_max;     /* inner iteration cap, >= 1 */
+  int32_t n_min;     /* minimum inner count before acceptance, >= 1 */
+  int32_t corrector; /* msc_corrector */
+  int32_t storage;   /* msc_storage */
+  int32_t inputs_on_device; /* see conventions */
+  int32_t reserved0;
+  void* stream;      /* hipStream_t, or NULL */
+  /* Optional device allocator (e.g. a framework's caching allocator).  When
+   * alloc_fn is NULL the library uses hipMalloc/hipFree. */
+  void* (*alloc_fn)(size_t bytes, void* user);
+  void (*free_fn)(void* ptr, void* user);
+  void* alloc_user;
+} msc_params;
+
+/* Per physical step record (Alg. 1; Eq. rho-observed for rho_obs). */
+typedef struct msc_step_stats {
+  int32_t q;         /* BDF order used: 1 on the first step after a reset, else 2 */
+  int32_t iters;     /* inner sweeps performed (the accepted one included) */
+  double R_first;    /* raw residual RMS of the first sweep */
+  double R_final;    /* raw residual RMS of the last sweep */
+  double rho_obs;    /* tail geometric-mean contraction, NaN if fewer than 3 residuals */
+  int32_t converged; /* 1 if accepted */
+  int32_t reserved;
+} msc_step_stats;
+
+typedef struct msc_ctx msc_ctx;
+
+/* Fill *p with the paper's operating point (nu = 1/6, Lambda = 1/4 so
+ * tau+ = tau- = 1; K_max = 300; n_min = 2 in 2D, 1 in 3D; shadow corrector;
+ * FP64 storage) for a cubic/square grid of side n and the given dt and eps
+ * (Sec. 4.1, Tab. 1).  Returns MSC_ERR_INVALID_ARG for an unknown lattice. */
+msc_status msc_params_default(msc_params* p, int32_t lattice, int32_t n, double dt, double eps);
+
+/* Create a context (paper Sec. 4.1 initial state).
+ * phat0: N_sites FP64, u0: d*N_sites FP64, canonical order (see top).
+ * Sets f^0 = feq(phat0, u0) (Eq. feq) and m^0 = P f^0 (Eq. moments); the next
+ * BDF step is BDF1 (Eq. bdf2).  Inputs are copied during the call.
+ * Errors: MSC_ERR_INVALID_ARG (extent not a power of two or < 4, tau <= 1/2,
+ * dt <= 0, eps <= 0, k_max < 1, n_min < 1, unknown lattice/storage/corrector,
+ * NULL pointers); MSC_ERR_OUT_OF_MEMORY; MSC_ERR_DEVICE; MSC_ERR_UNSUPPORTED
+ * for a grid larger than the transform kernels support (2D: 4096 per side in
+ * FP32, 2048 in FP64; 3D: 512).  *out is owned by the library until
+ * msc_free. */
+msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, msc_ctx** out);
+
+/* Advance nsteps physical steps by Algorithm 1 (or Picard with
+ * MSC_CORRECTOR_PICARD): BDF1 on the first step after a reset, BDF2 after
+ * (Eq. bdf2); initial trial by population-history extrapolation; acceptance
+ * when the inner count >= n_min and the raw residual RMS < eps; on acceptance
+ * m^{n+1} = R(f_T) with the step's histories, then the histories rotate
+ * (Sec. 3.1).  stats: NULL or an array of nsteps records (caller-owned).
+ * Errors: MSC_ERR_NONCONVERGED (K_max reached) or MSC_ERR_NONFINITE: the
+ * context stays at the last accepted step and stats are filled up to and
+ * including the failing step.  MSC_ERR_INVALID_ARG for nsteps < 0. */
+msc_status msc_bdf2_step(msc_ctx* c, int32_t nsteps, msc_step_stats* stats);
+
+/* Advance nsteps lattice steps of the source-free TRT map (the sweep with
+ * a = 0, h = 0: m = P f, no source; Sec. 4.1: the explicit baseline uses the
+ * same collision and streaming kernels).  Resets the BDF history: the next
+ * msc_bdf2_step is BDF1 from the current state with m^n = P f^n.
+ * Errors: MSC_ERR_INVALID_ARG (nsteps < 0); MSC_ERR_NONFINITE when the final
+ * state holds a non-finite value (checked once at the end). */
+msc_status msc_explicit_step(msc_ctx* c, int64_t nsteps);
+
+/* Current hydrodynamic field: after BDF steps m^n = R(f^n) with that step's
+ * histories (Alg. 1); after explicit steps or msc_set_populations, P f.
+ * phat: N_sites FP64, u: d*N_sites FP64 (host, or device if flagged). */
+msc_status msc_moments(msc_ctx* c, double* phat, double* u);
+
+/* Release everything; NULL-safe. */
+void msc_free(msc_ctx* c);
+
+const char* msc_status_string(msc_status s);
+/* Message of the last failure on this context; valid until the next call. */
+const char* msc_last_error(const msc_ctx* c);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostic and test entry points.  Same conventions and error codes.      */
+
+/* Canonical index tables computed by the device with the index arithmetic
+ * the kernels use.  nbr: Q*N_sites int32, nbr[k*N_sites + s] = site of
+ * (x + c_k) mod N (push target, Eq. sweep); signed_idx: n[0] + n[1] (+ n[2])
+ * int32, the signed wavenumber index of Eq. (wavenumbers) per axis; mask:
+ * N_sites uint8, chi of Eq. (shadow-mask) (1 where 4|j_alpha| <= N for every
+ * alpha).  Any pointer may be NULL to skip that table.  Host buffers. */
+msc_status msc_export_tables(msc_ctx* c, int32_t* nbr, int32_t* signed_idx, uint8_t* mask);
+
+/* Copy the current populations f^n to / from a host FP64 array
+ * (Q*N_sites).  msc_set_populations rounds to the storage precision, sets
+ * m^n = P f and resets the BDF history (next step BDF1). */
+msc_status msc_get_populations(msc_ctx* c, double* f);
+msc_status msc_set_populations(msc_ctx* c, const double* f);
+
+/* One evaluation of the sweep T_{q,h}(f) (Eq. sweep) with its raw residual
+ * (Eq. residual), on the device.  f: Q*N_sites, h: (d+1)*N_sites (NULL
+ * means h = 0), a: the BDF coefficient a_q (0 for the source-free map).
+ * Outputs (any may be NULL): fT (Q*N_sites), Pr ((d+1)*N_sites, the residual
+ * moments P r), R (scalar RMS).  Host FP64 arrays.  Does not change the
+ * context's march state. */
+msc_status msc_sweep(msc_ctx* c, const double* f, const double* h, double a, double* fT,
+                     double* Pr, double* R);
+
+/* One corrected iteration (Alg. 1 body): fT = T(f), r = fT - f,
+ * dm = F^{-1}[chi H^{-1} F[P r]] (Eq. schur, shadow-update) and
+ * f_next = fT + E dm (Eq. lift).  Outputs (any may be NULL): f_next, dm
+ * ((d+1)*N_sites), R.  Host FP64.  Does not change the march state. */
+msc_status msc_correct(msc_ctx* c, const double* f, const double* h, double a, double* f_next,
+                       double* dm, double* R);
+
+/* Replay a recorded inner schedule: the next nsteps BDF steps accept at
+ * exactly K[i] sweeps regardless of eps (K[i] >= 1).  K == NULL or
+ * nsteps == 0 clears it.  The schedule is consumed by msc_bdf2_step. */
+msc_status msc_set_schedule(msc_ctx* c, const int32_t* K, int32_t nsteps);
+
+/* Checkpoint of the march state: f^n, f^{n-1}, f^{n-2} (3*Q*N_sites),
+ * m^n, m^{n-1} (2*(d+1)*N_sites) as FP64 host arrays, and the number of BDF
+ * steps accepted since the last reset.  msc_state_size gives the FP64 count
+ * of the array part. */
+msc_status msc_state_size(const msc_ctx* c, int64_t* n_doubles);
+msc_status msc_get_state(msc_ctx* c, double* state, int64_t* bdf_count);
+msc_status msc_set_state(msc_ctx* c, const double* state, int64_t bdf_count);
+
+/* Kernel timing for roofline reports: when enabled, every launch of the
+ * population sweep kernel is bracketed by HIP events on the context's stream
+ * and its duration accumulated.  msc_kernel_time returns the total seconds,
+ * launch count and algorithmic bytes per launch of the sweep (explicit and
+ * dual-time launches counted separately: kind 0 = dual-time sweep, 1 =
+ * explicit sweep).  Enabling resets the counters. */
+msc_status msc_set_kernel_timing(msc_ctx* c, int32_t enable);
+msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* launches,
+                           double* bytes_per_launch);
+
+/* Launch-shape knobs for tuning sweeps: key 2 = physical steps enqueued per
+ * host synchronisation (>= 1, default 32), 3 = speculative inner iterations
+ * enqueued beyond the previous step's count (>= 0, default 1), 4 = capture
+ * explicit-march chunks in HIP graphs (0/1, default 1).  Results do not
+ * depend on these.  MSC_ERR_INVALID_ARG for an unknown key. */
+msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSC_H_ */

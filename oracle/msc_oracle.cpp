@@ -528,17 +528,19 @@ int orc_explicit(int d, const int* n, double wp, double wm, double* f, int64_t n
 }
 
 // Dual-time BDF march by Algorithm 1 (corrector = 1) or plain Picard
-// (corrector = 0), nsteps physical steps from (p0, u0).
+// (corrector = 0) from a full march state:
+//   state: f^n, f^{n-1}, f^{n-2} (3 Q NS) then m^n, m^{n-1} (2 (d+1) NS),
+//          updated in place to the state after the last accepted step;
+//   bdf_count: accepted BDF steps since the last reset (0 -> BDF1 next),
+//          updated in place.
 //   schedule: NULL for tolerance stopping; otherwise schedule[i] is the inner
 //             count at which step i is accepted (replay of a recorded run).
 //   stats:    nsteps records (may be NULL).
 //   Rhist:    optional nsteps*kmax residual histories (may be NULL).
-//   f_out:    Q*NS populations f^n after the march; m_out: (d+1)*NS, m^n.
-// On failure the outputs hold the last accepted state and *steps_done tells
+// On failure the state holds the last accepted step and *steps_done tells
 // how many steps were accepted.
-int orc_march(const orc_params* P, const double* p0, const double* u0, int nsteps,
-              const int* schedule, orc_step_stats* stats, double* Rhist, double* f_out,
-              double* m_out, int* steps_done) {
+int orc_march_state(const orc_params* P, double* state, int64_t* bdf_count, int nsteps,
+                    const int* schedule, orc_step_stats* stats, double* Rhist, int* steps_done) {
   const int d = P->d;
   if (d != 2 && d != 3) return ORC_ERR_INVALID;
   Lattice L = make_lattice(d);
@@ -551,24 +553,24 @@ int orc_march(const orc_params* P, const double* p0, const double* u0, int nstep
   const int mcap = (d == 2) ? 10 : 8;           // Eq. (rho-observed) window
 
   // f^n, f^{n-1}, f^{n-2}; m^n, m^{n-1}
-  std::vector<double> fn(FQ), fn1(FQ), fn2(FQ), mn(FM), mn1(FM);
-  orc_init_populations(d, P->n, p0, u0, fn.data());
-  reconstruct(L, G, fn.data(), nullptr, 0.0, mn.data());  // m^0 = P f^0
-  mn1 = mn;
+  std::vector<double> fn(state, state + FQ), fn1(state + FQ, state + 2 * FQ),
+      fn2(state + 2 * FQ, state + 3 * FQ), mn(state + 3 * FQ, state + 3 * FQ + FM),
+      mn1(state + 3 * FQ + FM, state + 3 * FQ + 2 * FM);
   std::vector<double> f(FQ), fT(FQ), Pr(FM), dm(FM), h(FM), mnew(FM);
   std::vector<double> Rl;
   int status = ORC_OK, done = 0;
+  int64_t bc = *bdf_count;
   for (int step = 0; step < nsteps; ++step) {
-    // Eq. (bdf2): BDF1 on the first physical step, BDF2 afterwards.
-    const int q = (step == 0) ? 1 : 2;
+    // Eq. (bdf2): BDF1 on the first physical step after a reset, BDF2 after.
+    const int q = (bc == 0) ? 1 : 2;
     const double a = (q == 1) ? 1.0 / P->dt : 3.0 / (2.0 * P->dt);
     for (size_t i = 0; i < FM; ++i)
       h[i] = (q == 1) ? mn[i] / P->dt : (4.0 * mn[i] - mn1[i]) / (2.0 * P->dt);
     // Initial trial by population-history extrapolation (Sec. 3.1).
     for (size_t i = 0; i < FQ; ++i) {
-      if (step == 0)
+      if (bc == 0)
         f[i] = fn[i];
-      else if (step == 1)
+      else if (bc == 1)
         f[i] = 2.0 * fn[i] - fn1[i];
       else
         f[i] = 3.0 * fn[i] - 3.0 * fn1[i] + fn2[i];
@@ -626,12 +628,50 @@ int orc_march(const orc_params* P, const double* p0, const double* u0, int nstep
       if (status == ORC_OK) status = ORC_ERR_NONCONVERGED;
       break;
     }
+    ++bc;
     ++done;
   }
-  if (f_out) std::memcpy(f_out, fn.data(), sizeof(double) * FQ);
-  if (m_out) std::memcpy(m_out, mn.data(), sizeof(double) * FM);
+  std::memcpy(state, fn.data(), sizeof(double) * FQ);
+  std::memcpy(state + FQ, fn1.data(), sizeof(double) * FQ);
+  std::memcpy(state + 2 * FQ, fn2.data(), sizeof(double) * FQ);
+  std::memcpy(state + 3 * FQ, mn.data(), sizeof(double) * FM);
+  std::memcpy(state + 3 * FQ + FM, mn1.data(), sizeof(double) * FM);
+  *bdf_count = bc;
   if (steps_done) *steps_done = done;
   return status;
+}
+
+// Initial march state of Sec. 4.1: f^0 = feq(p0, u0), m^0 = P f^0 (the
+// moment-history reading m^0 = P f^0); the unused history slots are copies.
+int orc_initial_state(int d, const int* n, const double* p0, const double* u0, double* state) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  const size_t FQ = (size_t)L.Q * G.NS, FM = (size_t)(d + 1) * G.NS;
+  orc_init_populations(d, n, p0, u0, state);
+  std::memcpy(state + FQ, state, sizeof(double) * FQ);
+  std::memcpy(state + 2 * FQ, state, sizeof(double) * FQ);
+  reconstruct(L, G, state, nullptr, 0.0, state + 3 * FQ);
+  std::memcpy(state + 3 * FQ + FM, state + 3 * FQ, sizeof(double) * FM);
+  return ORC_OK;
+}
+
+// March from the initial fields (p0, u0); f_out / m_out receive f^n, m^n.
+int orc_march(const orc_params* P, const double* p0, const double* u0, int nsteps,
+              const int* schedule, orc_step_stats* stats, double* Rhist, double* f_out,
+              double* m_out, int* steps_done) {
+  const int d = P->d;
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, P->n);
+  const size_t FQ = (size_t)L.Q * G.NS, FM = (size_t)(d + 1) * G.NS;
+  std::vector<double> state(3 * FQ + 2 * FM);
+  orc_initial_state(d, P->n, p0, u0, state.data());
+  int64_t bc = 0;
+  int rc = orc_march_state(P, state.data(), &bc, nsteps, schedule, stats, Rhist, steps_done);
+  if (f_out) std::memcpy(f_out, state.data(), sizeof(double) * FQ);
+  if (m_out) std::memcpy(m_out, state.data() + 3 * FQ, sizeof(double) * FM);
+  return rc;
 }
 
 }  // extern "C"

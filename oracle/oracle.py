@@ -86,7 +86,10 @@ def lib():
                                    ctypes.c_int64]
         L.orc_march.argtypes = [ctypes.POINTER(OrcParams), _dp, _dp, ctypes.c_int, _ip,
                                 ctypes.POINTER(OrcStepStats), _dp, _dp, _dp, _ip]
-        for name in ("orc_lattice", "orc_sweep", "orc_shadow", "orc_corrected_iteration", "orc_fft",
+        L.orc_march_state.argtypes = [ctypes.POINTER(OrcParams), _dp, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int, _ip, ctypes.POINTER(OrcStepStats), _dp, _ip]
+        L.orc_initial_state.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp]
+        for name in ("orc_march_state", "orc_initial_state", "orc_lattice", "orc_sweep", "orc_shadow", "orc_corrected_iteration", "orc_fft",
                      "orc_tables", "orc_init_populations", "orc_moments", "orc_explicit",
                      "orc_march"):
             getattr(L, name).restype = ctypes.c_int
@@ -247,6 +250,46 @@ class MarchResult:
     m: np.ndarray
     stats: list
     Rhist: np.ndarray | None
+
+
+def initial_state(p0, u0):
+    """Full march state (f^n, f^{n-1}, f^{n-2}, m^n, m^{n-1}) flattened, as
+    the library's msc_get_state lays it out, at the initial condition."""
+    p0, u0 = _c64(p0), _c64(u0)
+    d = u0.shape[0]
+    Q = 9 if d == 2 else 19
+    NS = p0.size
+    st = np.zeros(3 * Q * NS + 2 * (d + 1) * NS)
+    rc = lib().orc_initial_state(d, _dims(p0.shape), _p(p0), _p(u0), _p(st))
+    assert rc == 0
+    return st
+
+
+def _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus):
+    P = OrcParams()
+    P.d = d
+    P.n = (ctypes.c_int * 3)(*(list(shape) + [1] * (3 - len(shape))))
+    P.tau_plus, P.tau_minus, P.dt, P.eps = tau_plus, tau_minus, dt, eps
+    P.kmax, P.nmin, P.corrector = kmax, nmin, corrector
+    return P
+
+
+def march_state(state, bdf_count, shape, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1,
+                tau_plus=1.0, tau_minus=1.0, schedule=None):
+    """Advance a full march state; returns (status, new_state, bdf_count, stats)."""
+    d = len(shape)
+    P = _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus)
+    st = np.array(state, dtype=np.float64, copy=True)
+    bc = ctypes.c_int64(int(bdf_count))
+    stats = (OrcStepStats * max(nsteps, 1))()
+    sched = np.ascontiguousarray(schedule, dtype=np.int32) if schedule is not None else None
+    done = ctypes.c_int32()
+    rc = lib().orc_march_state(ctypes.byref(P), _p(st), ctypes.byref(bc), nsteps,
+                               sched.ctypes.data_as(_ip) if sched is not None else None, stats, None,
+                               ctypes.byref(done))
+    out = [dict(q=s.q, iters=s.iters, R_first=s.R_first, R_final=s.R_final, rho_obs=s.rho_obs,
+                converged=s.converged) for s in stats[:nsteps]]
+    return rc, st, bc.value, out
 
 
 def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_plus=1.0,

@@ -1,0 +1,114 @@
+// Shared definitions of the HIP library: lattice traits, the device control
+// block that sequences Algorithm 1 on the GPU, and kernel argument records.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msc {
+
+// ------------------------------------------------------------- lattices --
+// Discrete velocities, weights and opposites of App. A (Eq. d2q9, d3q19).
+// The sweep walks planes along x; a plane is addressed by (p1, p2) with p2
+// the contiguous index: (p1, p2) = (-, y) in 2D and (y, z) in 3D.  c1/c2 are
+// the velocity components along p1/p2.
+struct D2Q9 {
+  static constexpr int D = 2, Q = 9;
+  __host__ __device__ static constexpr int cx(int k) {
+    return (k == 1 || k == 5 || k == 8) ? 1 : ((k == 3 || k == 6 || k == 7) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cy(int k) {
+    return (k == 2 || k == 5 || k == 6) ? 1 : ((k == 4 || k == 7 || k == 8) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr int c1(int) { return 0; }
+  __host__ __device__ static constexpr int c2(int k) { return cy(k); }
+  __host__ __device__ static constexpr int opp(int k) {
+    return k == 0 ? 0 : (k <= 4 ? ((k + 1) % 4) + 1 : ((k - 5 + 2) % 4) + 5);
+  }
+  __host__ __device__ static constexpr double w(int k) {
+    return k == 0 ? 4.0 / 9.0 : (k <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+struct D3Q19 {
+  static constexpr int D = 3, Q = 19;
+  __host__ __device__ static constexpr int cx(int k) {
+    return (k == 1 || k == 7 || k == 9 || k == 11 || k == 13)
+               ? 1
+               : ((k == 2 || k == 8 || k == 10 || k == 12 || k == 14) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cy(int k) {
+    return (k == 3 || k == 7 || k == 10 || k == 15 || k == 17)
+               ? 1
+               : ((k == 4 || k == 8 || k == 9 || k == 16 || k == 18) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cz(int k) {
+    return (k == 5 || k == 11 || k == 14 || k == 15 || k == 18)
+               ? 1
+               : ((k == 6 || k == 12 || k == 13 || k == 16 || k == 17) ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int c1(int k) { return cy(k); }
+  __host__ __device__ static constexpr int c2(int k) { return cz(k); }
+  __host__ __device__ static constexpr int opp(int k) { return k == 0 ? 0 : (k % 2 == 1 ? k + 1 : k - 1); }
+  __host__ __device__ static constexpr double w(int k) {
+    return k == 0 ? 1.0 / 3.0 : (k <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+template <class L>
+__host__ __device__ constexpr int ca(int k, int a) {
+  return a == 0 ? L::cx(k) : (a == 1 ? L::cy(k) : L::cz(k));
+}
+
+// ------------------------------------------------------- control block --
+// Algorithm 1 runs as a sequence of kernels enqueued ahead by the host.  The
+// device decides acceptance; every kernel launched for (step n, iteration
+// ell) first reads one 64-bit phase word and returns at once unless the march
+// is exactly at that point.  Only single-block kernels write the phase, so
+// the word every block of a grid reads is the same.
+enum : uint32_t { PH_RUNNING = 1, PH_ACCEPTED = 2, PH_FAILED = 3 };
+
+__host__ __device__ inline uint64_t make_phase(int n, int ell, uint32_t st) {
+  return ((uint64_t)(uint32_t)(n + 1) << 32) | ((uint64_t)(uint32_t)ell << 8) | st;
+}
+__host__ __device__ inline int phase_n(uint64_t p) { return (int)(uint32_t)(p >> 32) - 1; }
+__host__ __device__ inline int phase_ell(uint64_t p) { return (int)((p >> 8) & 0xFFFFFF); }
+__host__ __device__ inline uint32_t phase_state(uint64_t p) { return (uint32_t)(p & 0xFF); }
+
+// Before iteration ell of step n (setup of step n counts as "before ell = 1").
+__host__ __device__ inline bool phase_ready(uint64_t p, int n, int ell) {
+  if (ell == 1) return phase_state(p) == PH_ACCEPTED && phase_n(p) == n - 1;
+  return phase_state(p) == PH_RUNNING && phase_n(p) == n && phase_ell(p) == ell - 1;
+}
+// After sweep ell of step n, not accepted: the correction of ell runs.
+__host__ __device__ inline bool phase_correct(uint64_t p, int n, int ell) {
+  return phase_state(p) == PH_RUNNING && phase_n(p) == n && phase_ell(p) == ell;
+}
+// Step n accepted at sweep ell.
+__host__ __device__ inline bool phase_accepted(uint64_t p, int n, int ell) {
+  return phase_state(p) == PH_ACCEPTED && phase_n(p) == n && phase_ell(p) == ell;
+}
+
+struct StepStat {
+  int32_t q, iters;
+  double R_first, R_final, rho_obs;
+  int32_t converged, fail;
+};
+
+struct DevCtl {
+  uint64_t phase;
+  int32_t fail_code;
+  int32_t slot_hist[3];  // population buffer index of f^n, f^{n-1}, f^{n-2}
+  int32_t slot_w[2];     // the two working buffers of the inner iteration
+  int32_t slot_m[3];     // moment buffer index of m^n, m^{n-1} and the spare
+  int32_t pad;
+};
+
+// Population buffers (five, roles assigned through DevCtl slots).
+template <class T>
+struct FBufs {
+  T* p[5];
+};
+
+}  // namespace msc

@@ -1,0 +1,306 @@
+// Periodic macroscopic shadow correction (paper Sec. 3.2, Eq. shadow-update):
+// dm = F^{-1}[ chi(k) H^{-1}(k) F[P r](k) ] with the transform convention of
+// Eq. (fft-convention) (forward unnormalised, inverse 1/N_Omega), the signed
+// wavenumbers of Eq. (wavenumbers) and the rectangular mask of Eq.
+// (shadow-mask).  Only the masked band |j_alpha| <= N_alpha/4 is ever
+// materialised: the residual moments are real, so the contiguous axis keeps
+// j = 0..N/4 (the negative half follows by conjugate symmetry) and the other
+// axes keep |j| <= N/4.
+//
+// Transforms are radix-4 Stockham passes (one radix-2 pass when log2 N is
+// odd) on complex lines held in LDS, ping-ponging between two LDS arrays; the
+// twiddle table exp(-2 pi i t/N) is precomputed per axis.  The per-wavevector
+// 3x3 (2D) / 4x4 (3D) solve of Eq. (schur) runs in FP64 inside the kernel that
+// holds the full spectrum line of the last axis.
+#pragma once
+
+#include "msc_kernels.h"
+
+namespace msc {
+
+template <class CT>
+struct cpx {
+  CT x, y;
+};
+
+template <class CT>
+__device__ __forceinline__ cpx<CT> cmul(cpx<CT> a, cpx<CT> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class CT>
+__device__ __forceinline__ cpx<CT> cadd(cpx<CT> a, cpx<CT> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <class CT>
+__device__ __forceinline__ cpx<CT> csub(cpx<CT> a, cpx<CT> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+// multiply by +i (s > 0) or -i (s < 0)
+template <class CT>
+__device__ __forceinline__ cpx<CT> cmuli(cpx<CT> a, int s) {
+  return s > 0 ? cpx<CT>{-a.y, a.x} : cpx<CT>{a.y, -a.x};
+}
+
+// nt independent transforms of length N = 2^lg stored contiguously at
+// buf + t*N.  sign = -1 forward, +1 inverse (no scaling).  The caller has
+// synchronised after filling buf; returns the array holding the result (buf
+// or tmp), synchronised.
+template <class CT>
+__device__ cpx<CT>* lds_fft(cpx<CT>* buf, cpx<CT>* tmp, int lg, int nt, int sign,
+                            const cpx<CT>* __restrict__ tw) {
+  const int N = 1 << lg;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  cpx<CT>* a = buf;
+  cpx<CT>* b = tmp;
+  int Ns = 1;
+  for (int p = 0; p < (lg >> 1); ++p) {
+    const int lnb = lg - 2, nb = 1 << lnb;
+    const int tstride = N / (4 * Ns);
+    for (int j = tid; j < (nt << lnb); j += nth) {
+      const int t = j >> lnb, jj = j & (nb - 1);
+      const cpx<CT>* x = a + t * N;
+      cpx<CT>* y = b + t * N;
+      const int k = jj & (Ns - 1);
+      cpx<CT> w1 = tw[k * tstride], w2 = tw[2 * k * tstride], w3 = tw[3 * k * tstride];
+      if (sign > 0) {
+        w1.y = -w1.y;
+        w2.y = -w2.y;
+        w3.y = -w3.y;
+      }
+      const cpx<CT> v0 = x[jj];
+      const cpx<CT> v1 = cmul(x[jj + nb], w1);
+      const cpx<CT> v2 = cmul(x[jj + 2 * nb], w2);
+      const cpx<CT> v3 = cmul(x[jj + 3 * nb], w3);
+      const cpx<CT> s02 = cadd(v0, v2), d02 = csub(v0, v2);
+      const cpx<CT> s13 = cadd(v1, v3), d13 = cmuli(csub(v1, v3), sign);
+      const int base = ((jj - k) << 2) + k;
+      y[base] = cadd(s02, s13);
+      y[base + Ns] = cadd(d02, d13);
+      y[base + 2 * Ns] = csub(s02, s13);
+      y[base + 3 * Ns] = csub(d02, d13);
+    }
+    __syncthreads();
+    cpx<CT>* sw = a;
+    a = b;
+    b = sw;
+    Ns <<= 2;
+  }
+  if (lg & 1) {
+    const int lnb = lg - 1, nb = 1 << lnb;
+    const int tstride = N / (2 * Ns);
+    for (int j = tid; j < (nt << lnb); j += nth) {
+      const int t = j >> lnb, jj = j & (nb - 1);
+      const cpx<CT>* x = a + t * N;
+      cpx<CT>* y = b + t * N;
+      const int k = jj & (Ns - 1);
+      cpx<CT> w1 = tw[k * tstride];
+      if (sign > 0) w1.y = -w1.y;
+      const cpx<CT> v0 = x[jj];
+      const cpx<CT> v1 = cmul(x[jj + nb], w1);
+      const int base = ((jj - k) << 1) + k;
+      y[base] = cadd(v0, v1);
+      y[base + Ns] = csub(v0, v1);
+    }
+    __syncthreads();
+    a = b;
+  }
+  return a;
+}
+
+// Eq. (schur) at one wavevector, FP64.  r[0] = F[r_p], r[1..D] = F[r_m];
+// out[0] = dp, out[1..D] = du, each scaled by `scale` (the 1/N_Omega of the
+// inverse transform).
+template <int D>
+__device__ __forceinline__ void schur_solve(const double* kv, const double (*r)[2], double a, double nu,
+                                            double scale, double (*out)[2]) {
+  const double cs2 = 1.0 / 3.0;
+  double kk = 0.0;
+  for (int b = 0; b < D; ++b) kk += kv[b] * kv[b];
+  const double bc = a + nu * kk;
+  // k . r_m
+  double kr_re = 0.0, kr_im = 0.0;
+  for (int b = 0; b < D; ++b) {
+    kr_re += kv[b] * r[1 + b][0];
+    kr_im += kv[b] * r[1 + b][1];
+  }
+  // numerator r_p - i (k.r_m)/b ; -i*(x + iy) = y - ix
+  const double num_re = r[0][0] + kr_im / bc;
+  const double num_im = r[0][1] - kr_re / bc;
+  const double den = a + cs2 * kk / bc;
+  const double dp_re = num_re / den, dp_im = num_im / den;
+  out[0][0] = dp_re * scale;
+  out[0][1] = dp_im * scale;
+  for (int b = 0; b < D; ++b) {
+    // (r_b - cs2 i k_b dp)/b ; i*dp = (-dp_im, dp_re)
+    const double re = (r[1 + b][0] + cs2 * kv[b] * dp_im) / bc;
+    const double im = (r[1 + b][1] - cs2 * kv[b] * dp_re) / bc;
+    out[1 + b][0] = re * scale;
+    out[1 + b][1] = im * scale;
+  }
+}
+
+// Guard shared by the correction kernels: run only right after sweep ell of
+// step n without acceptance (Algorithm 1 mode), or always (diagnostic mode).
+struct CorrGuard {
+  const DevCtl* ctl;
+  int n, ell;
+  __device__ bool skip() const { return ctl && !phase_correct(ctl->phase, n, ell); }
+};
+
+// ---------------------------------------------------------------- 2D ----
+// Pass 1: forward transform along y (contiguous) of the three residual-moment
+// rows of each x, keeping j_y = 0..N_y/4.  Rows (r_p, r_x) share one complex
+// transform (real/imaginary packing); r_y takes a second one.
+template <class CT, class TM>
+struct Fft2Args {
+  CorrGuard g;
+  int Nx, Ny, lgx, lgy;
+  int NBy;      // N_y/4 + 1
+  int rows_per_block, cols_per_block;
+  const TM* Pr;            // 3 x Nx x Ny
+  cpx<CT>* spec;           // 3 x Nx x NBy
+  TM* dm;                  // 3 x Nx x Ny
+  const cpx<CT>* twx;      // Nx
+  const cpx<CT>* twy;      // Ny
+  double a, nu, inv_ns;
+};
+
+template <class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A) {
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int Ny = A.Ny, R = A.rows_per_block;
+  cpx<CT>* tmp = buf + 2 * R * Ny;
+  const int x0 = blockIdx.x * R;
+  const int64_t NS = (int64_t)A.Nx * Ny;
+  for (int i = threadIdx.x; i < R * Ny; i += blockDim.x) {
+    const int r = i / Ny, y = i - r * Ny;
+    const int64_t s = (int64_t)(x0 + r) * Ny + y;
+    buf[(2 * r) * Ny + y] = {(CT)A.Pr[s], (CT)A.Pr[NS + s]};
+    buf[(2 * r + 1) * Ny + y] = {(CT)A.Pr[2 * NS + s], (CT)0};
+  }
+  __syncthreads();
+  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgy, 2 * R, -1, A.twy);
+  const int NB = A.NBy;
+  for (int i = threadIdx.x; i < R * NB; i += blockDim.x) {
+    const int r = i / NB, j = i - r * NB;
+    const cpx<CT> z = out[(2 * r) * Ny + j];
+    const cpx<CT> zc = out[(2 * r) * Ny + ((Ny - j) & (Ny - 1))];
+    // unpack: F0 = (Z(j) + conj Z(-j))/2, F1 = (Z(j) - conj Z(-j))/(2i)
+    const cpx<CT> f0 = {(CT)0.5 * (z.x + zc.x), (CT)0.5 * (z.y - zc.y)};
+    const cpx<CT> f1 = {(CT)0.5 * (z.y + zc.y), (CT)0.5 * (zc.x - z.x)};
+    const int64_t o = (int64_t)(x0 + r) * NB + j;
+    const int64_t FS = (int64_t)A.Nx * NB;
+    A.spec[o] = f0;
+    A.spec[FS + o] = f1;
+    A.spec[2 * FS + o] = out[(2 * r + 1) * Ny + j];
+  }
+}
+
+// Pass 2: for a group of j_y columns, forward transform along x, the FP64
+// Schur solve on the band |j_x| <= N_x/4 (zero elsewhere), and the inverse
+// transform along x, in place in the band spectrum array.
+template <class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft2_cols_solve(Fft2Args<CT, TM> A) {
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int Nx = A.Nx, JB = A.cols_per_block, NB = A.NBy;
+  cpx<CT>* tmp = buf + 3 * JB * Nx;
+  const int j0 = blockIdx.x * JB;
+  const int64_t FS = (int64_t)Nx * NB;
+  // transform t = f*JB + c holds column j0 + c of field f
+  for (int i = threadIdx.x; i < 3 * JB * Nx; i += blockDim.x) {
+    const int c = i % JB;
+    const int rest = i / JB;
+    const int x = rest % Nx, f = rest / Nx;
+    const int j = j0 + c;
+    buf[(f * JB + c) * Nx + x] = (j < NB) ? A.spec[f * FS + (int64_t)x * NB + j] : cpx<CT>{0, 0};
+  }
+  __syncthreads();
+  cpx<CT>* F = lds_fft<CT>(buf, tmp, A.lgx, 3 * JB, -1, A.twx);
+  cpx<CT>* G = (F == buf) ? tmp : buf;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int i = threadIdx.x; i < JB * Nx; i += blockDim.x) {
+    const int c = i / Nx, jx = i - c * Nx;
+    const int jy = j0 + c;
+    const int sjx = signed_index(jx, Nx);
+    if (jy < NB && in_band(sjx, Nx)) {
+      double kv[2] = {two_pi * sjx / Nx, two_pi * jy / A.Ny};
+      double r[3][2], o[3][2];
+      for (int f = 0; f < 3; ++f) {
+        const cpx<CT> v = F[(f * JB + c) * Nx + jx];
+        r[f][0] = (double)v.x;
+        r[f][1] = (double)v.y;
+      }
+      schur_solve<2>(kv, r, A.a, A.nu, A.inv_ns, o);
+      for (int f = 0; f < 3; ++f) G[(f * JB + c) * Nx + jx] = {(CT)o[f][0], (CT)o[f][1]};
+    } else {
+      for (int f = 0; f < 3; ++f) G[(f * JB + c) * Nx + jx] = {(CT)0, (CT)0};
+    }
+  }
+  __syncthreads();
+  cpx<CT>* H = lds_fft<CT>(G, F, A.lgx, 3 * JB, +1, A.twx);
+  for (int i = threadIdx.x; i < 3 * JB * Nx; i += blockDim.x) {
+    const int c = i % JB;
+    const int rest = i / JB;
+    const int x = rest % Nx, f = rest / Nx;
+    const int j = j0 + c;
+    if (j < NB) A.spec[f * FS + (int64_t)x * NB + j] = H[(f * JB + c) * Nx + x];
+  }
+}
+
+// Pass 3: inverse transform along y from the half band to real rows.  The
+// band of field f at x is extended by conjugate symmetry (Z(N - j) =
+// conj Z(j)); fields 0 and 1 share one complex inverse transform (real and
+// imaginary parts), field 2 uses the real part of a second one.
+template <class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft2_rows_inv(Fft2Args<CT, TM> A) {
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int Ny = A.Ny, R = A.rows_per_block, NB = A.NBy;
+  cpx<CT>* tmp = buf + 2 * R * Ny;
+  const int x0 = blockIdx.x * R;
+  const int64_t FS = (int64_t)A.Nx * NB;
+  for (int i = threadIdx.x; i < R * Ny; i += blockDim.x) {
+    const int r = i / Ny, j = i - r * Ny;
+    const int64_t o = (int64_t)(x0 + r) * NB;
+    cpx<CT> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
+    if (j < NB) {
+      a0 = A.spec[o + j];
+      a1 = A.spec[FS + o + j];
+      a2 = A.spec[2 * FS + o + j];
+      if (j == 0) {
+        a0.y = 0;
+        a1.y = 0;
+        a2.y = 0;
+      }
+    } else if (Ny - j < NB) {
+      const int jj = Ny - j;
+      a0 = A.spec[o + jj];
+      a1 = A.spec[FS + o + jj];
+      a2 = A.spec[2 * FS + o + jj];
+      a0.y = -a0.y;
+      a1.y = -a1.y;
+      a2.y = -a2.y;
+    }
+    // pack a0 + i a1
+    buf[(2 * r) * Ny + j] = {a0.x - a1.y, a0.y + a1.x};
+    buf[(2 * r + 1) * Ny + j] = a2;
+  }
+  __syncthreads();
+  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgy, 2 * R, +1, A.twy);
+  const int64_t NS = (int64_t)A.Nx * Ny;
+  for (int i = threadIdx.x; i < R * Ny; i += blockDim.x) {
+    const int r = i / Ny, y = i - r * Ny;
+    const int64_t s = (int64_t)(x0 + r) * Ny + y;
+    const cpx<CT> z = out[(2 * r) * Ny + y];
+    A.dm[s] = (TM)z.x;
+    A.dm[NS + s] = (TM)z.y;
+    A.dm[2 * NS + s] = (TM)out[(2 * r + 1) * Ny + y].x;
+  }
+}
+
+}  // namespace msc

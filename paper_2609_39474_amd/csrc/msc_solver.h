@@ -1,0 +1,67 @@
+// Host runtime of the library: one Solver<L, T> per (lattice, storage type)
+// owns the device buffers and sequences the kernels.  The C ABI in
+// msc_api.cpp validates arguments and forwards to the SolverBase interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/msc.h"
+
+namespace msc {
+
+struct DeviceError {
+  hipError_t err;
+  std::string what;
+};
+
+struct Geometry {
+  int d, Q;
+  int n[3];       // user extents (x, y, z)
+  int N0, N1, N2; // sweep frame: x, p1, p2
+  int64_t NS;
+};
+
+struct Tuning {
+  int sweep_tile = 0;     // 0 = automatic
+  int sweep_strip = 0;    // planes per strip, 0 = automatic
+  int batch_steps = 32;   // physical steps enqueued between host synchronisations
+  int spec_extra = 1;     // speculative iterations beyond the last step's count
+  int use_graph = 1;      // capture explicit chunks in hipGraphs
+};
+
+class SolverBase {
+ public:
+  virtual ~SolverBase() {}
+  virtual msc_status init(const double* phat0, const double* u0, bool on_device) = 0;
+  virtual msc_status bdf2_step(int32_t nsteps, msc_step_stats* stats) = 0;
+  virtual msc_status explicit_step(int64_t nsteps) = 0;
+  virtual msc_status moments(double* phat, double* u, bool on_device) = 0;
+  virtual msc_status export_tables(int32_t* nbr, int32_t* sidx, uint8_t* mask) = 0;
+  virtual msc_status get_populations(double* f) = 0;
+  virtual msc_status set_populations(const double* f) = 0;
+  virtual msc_status sweep(const double* f, const double* h, double a, double* fT, double* Pr,
+                           double* R) = 0;
+  virtual msc_status correct(const double* f, const double* h, double a, double* fnext, double* dm,
+                             double* R) = 0;
+  virtual msc_status set_schedule(const int32_t* K, int32_t nsteps) = 0;
+  virtual int64_t state_size() const = 0;
+  virtual msc_status get_state(double* state, int64_t* bdf_count) = 0;
+  virtual msc_status set_state(const double* state, int64_t bdf_count) = 0;
+  virtual msc_status set_kernel_timing(int enable) = 0;
+  virtual msc_status kernel_time(int kind, double* seconds, int64_t* launches, double* bytes) = 0;
+  virtual Tuning& tuning() = 0;
+
+  std::string last_error;
+  bool broken = false;
+};
+
+// Factory per (lattice, storage); each lives in its own translation unit.
+SolverBase* make_solver_d2_fp64(const msc_params& p, const Geometry& g, hipStream_t s);
+SolverBase* make_solver_d2_fp32(const msc_params& p, const Geometry& g, hipStream_t s);
+SolverBase* make_solver_d3_fp64(const msc_params& p, const Geometry& g, hipStream_t s);
+SolverBase* make_solver_d3_fp32(const msc_params& p, const Geometry& g, hipStream_t s);
+
+}  // namespace msc

@@ -192,3 +192,21 @@ def test_failure_modes(orc):
     # schedule replay accepts at the given counts regardless of eps
     r2 = orc.march(p0, u0, dt=64.0, nsteps=3, eps=1e-30, kmax=10, nmin=1, schedule=[3, 2, 4])
     assert r2.status == 0 and [s["iters"] for s in r2.stats] == [3, 2, 4]
+
+
+def test_march_state_composes(orc):
+    """Stepping the full state one step at a time reproduces the one-shot march
+    bit for bit (same arithmetic, same order)."""
+    N = 16
+    p0, u0 = W.random_field_2d(N, NU / N, seed=5, jmax=4)
+    full = orc.march(p0, u0, dt=48.0, nsteps=4, eps=1e-12, nmin=2)
+    st, bc = orc.initial_state(p0, u0), 0
+    for n in range(4):
+        rc, st, bc, _ = orc.march_state(st, bc, (N, N), dt=48.0, nsteps=1, eps=1e-12, nmin=2,
+                                        schedule=[full.stats[n]["iters"]])
+        assert rc == 0
+    Q = 9
+    NS = N * N
+    np.testing.assert_array_equal(st[:Q * NS].reshape(full.f.shape), full.f)
+    np.testing.assert_array_equal(st[3 * Q * NS:3 * Q * NS + 3 * NS].reshape(full.m.shape), full.m)
+    assert bc == 4
