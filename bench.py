@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--workload", default="rand2d_n256_fp32")
     ap.add_argument("--dt", type=float, default=256.0)
     ap.add_argument("--eps", type=float, default=1e-8)
+    ap.add_argument("--extrap", type=int, default=2,
+                    help="population states in the initial-trial extrapolation (0: paper rule, up to cubic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the beyond-cache sweep measurement")
     args = ap.parse_args()
@@ -86,8 +88,9 @@ def main():
     storage = cfg["storage"]
     dtype = {"fp64": "f64", "fp32": "f32"}[storage]
 
-    def solver(st=storage, corrector="shadow", eps=args.eps, ddt=dt):
-        p = msc.make_params(d, N, dt=ddt, eps=eps, storage=st, corrector=corrector, n_min=cfg["nmin"])
+    def solver(st=storage, corrector="shadow", eps=args.eps, ddt=dt, extrap=args.extrap):
+        p = msc.make_params(d, N, dt=ddt, eps=eps, storage=st, corrector=corrector, n_min=cfg["nmin"],
+                            extrap_states=extrap)
         return msc.Solver(p, p0, u0, stream=stream)
 
     # ---- warmup (separate context; compiles nothing, fills caches/queues)
@@ -139,6 +142,20 @@ def main():
     e.close()
     log(f"[bench] explicit: {t_exp:.3f} s for {nexp} lattice steps; sweep avg {xsec / max(xl, 1) * 1e6:.2f} us")
 
+    # ---- the paper's extrapolation rule (up to cubic) on the same workload
+    s = solver(extrap=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc0, st0 = s.bdf2_step(K, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t_paper = time.perf_counter() - t0
+    s.close()
+    done0 = sum(1 for x in st0 if x["converged"])
+    paper_rule = {"status": int(rc0), "steps_accepted": done0, "steps_requested": K, "seconds": t_paper,
+                  "mean_inner": float(np.mean([x["iters"] for x in st0[:max(done0, 1)]])),
+                  "last_iters": [x["iters"] for x in st0[max(0, done0 - 3):done0 + 1]]}
+    log(f"[bench] paper extrapolation rule: status {rc0}, {done0}/{K} steps accepted")
+
     # ---- FP64 explicit reference endpoint and accuracy gates
     r = solver(st="fp64", corrector="picard")
     r.explicit_step(nexp)
@@ -168,7 +185,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": "D2Q9" if d == 2 else "D3Q19", "N": N, "Re": cfg["Re"],
                    "nu": nu, "dt": dt, "eps": args.eps, "horizon_lattice_steps": T_sim,
-                   "viscous_times": T_sim / tnu, "storage": storage, "n_min": cfg["nmin"], "K_max": 300},
+                   "viscous_times": T_sim / tnu, "storage": storage, "n_min": cfg["nmin"], "K_max": 300,
+                   "extrap_states": args.extrap},
+        "paper_extrapolation_rule": paper_rule,
         "explicit_wall_s_per_viscous_time": value_exp,
         "speedup_vs_explicit": t_exp / t_msc,
         "accuracy": {"msc_rel_vs_fp64_explicit": e_msc, "fp32_explicit_rel_vs_fp64_explicit": e_exp32,

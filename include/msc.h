@@ -78,7 +78,12 @@ typedef struct msc_params {
   int32_t corrector; /* msc_corrector */
   int32_t storage;   /* msc_storage */
   int32_t inputs_on_device; /* see conventions */
-  int32_t reserved0;
+  /* Population states used for the initial trial of a physical step.  0 (the
+   * default) is the paper's rule (Sec. 3.1): f^n, then 2 f^n - f^{n-1}, then
+   * 3 f^n - 3 f^{n-1} + f^{n-2} once enough accepted states exist.  1, 2, 3
+   * cap it at constant, linear, cubic.  A cap below 3 is a deviation from the
+   * paper; it changes iteration counts only, never the fixed point. */
+  int32_t extrap_states;
   void* stream;      /* hipStream_t, or NULL */
   /* Optional device allocator (e.g. a framework's caching allocator).  When
    * alloc_fn is NULL the library uses hipMalloc/hipFree. */

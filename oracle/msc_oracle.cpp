@@ -377,6 +377,8 @@ struct orc_params {
   int kmax;         // inner cap
   int nmin;         // minimum accepted inner count
   int corrector;    // 0 = plain Picard, 1 = periodic shadow correction
+  int extrap_states; // 0 = the paper's extrapolation rule; 1, 2, 3 cap it at
+                     // constant, linear, cubic (a non-paper option)
 };
 
 struct orc_step_stats {
@@ -567,10 +569,12 @@ int orc_march_state(const orc_params* P, double* state, int64_t* bdf_count, int 
     for (size_t i = 0; i < FM; ++i)
       h[i] = (q == 1) ? mn[i] / P->dt : (4.0 * mn[i] - mn1[i]) / (2.0 * P->dt);
     // Initial trial by population-history extrapolation (Sec. 3.1).
+    const int64_t cap = (P->extrap_states == 0) ? 2 : P->extrap_states - 1;
+    const int64_t order = std::min<int64_t>(bc, cap);
     for (size_t i = 0; i < FQ; ++i) {
-      if (bc == 0)
+      if (order == 0)
         f[i] = fn[i];
-      else if (bc == 1)
+      else if (order == 1)
         f[i] = 2.0 * fn[i] - fn1[i];
       else
         f[i] = 3.0 * fn[i] - 3.0 * fn1[i] + fn2[i];

@@ -44,6 +44,7 @@ class OrcParams(ctypes.Structure):
         ("kmax", ctypes.c_int),
         ("nmin", ctypes.c_int),
         ("corrector", ctypes.c_int),
+        ("extrap_states", ctypes.c_int),
     ]
 
 
@@ -265,8 +266,9 @@ def initial_state(p0, u0):
     return st
 
 
-def _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus):
+def _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extrap_states=0):
     P = OrcParams()
+    P.extrap_states = extrap_states
     P.d = d
     P.n = (ctypes.c_int * 3)(*(list(shape) + [1] * (3 - len(shape))))
     P.tau_plus, P.tau_minus, P.dt, P.eps = tau_plus, tau_minus, dt, eps
@@ -275,10 +277,10 @@ def _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus):
 
 
 def march_state(state, bdf_count, shape, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1,
-                tau_plus=1.0, tau_minus=1.0, schedule=None):
+                tau_plus=1.0, tau_minus=1.0, schedule=None, extrap_states=0):
     """Advance a full march state; returns (status, new_state, bdf_count, stats)."""
     d = len(shape)
-    P = _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus)
+    P = _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extrap_states)
     st = np.array(state, dtype=np.float64, copy=True)
     bc = ctypes.c_int64(int(bdf_count))
     stats = (OrcStepStats * max(nsteps, 1))()
@@ -293,7 +295,7 @@ def march_state(state, bdf_count, shape, *, dt, nsteps, eps=1e-10, kmax=300, nmi
 
 
 def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_plus=1.0,
-          tau_minus=1.0, schedule=None, keep_rhist=False) -> MarchResult:
+          tau_minus=1.0, schedule=None, keep_rhist=False, extrap_states=0) -> MarchResult:
     """Dual-time march by Algorithm 1 (corrector=1) or Picard (corrector=0)."""
     p0, u0 = _c64(p0), _c64(u0)
     d = u0.shape[0]
@@ -304,6 +306,7 @@ def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_p
     P.n = (ctypes.c_int * 3)(*(list(shape) + [1] * (3 - len(shape))))
     P.tau_plus, P.tau_minus, P.dt, P.eps = tau_plus, tau_minus, dt, eps
     P.kmax, P.nmin, P.corrector = kmax, nmin, corrector
+    P.extrap_states = extrap_states
     st = (OrcStepStats * max(nsteps, 1))()
     f = np.zeros((Q,) + shape)
     m = np.zeros((d + 1,) + shape)

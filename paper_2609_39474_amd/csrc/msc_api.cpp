@@ -69,6 +69,7 @@ msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, 
     return MSC_ERR_INVALID_ARG;
   if (p->corrector != MSC_CORRECTOR_PICARD && p->corrector != MSC_CORRECTOR_SHADOW)
     return MSC_ERR_INVALID_ARG;
+  if (p->extrap_states < 0 || p->extrap_states > 3) return MSC_ERR_INVALID_ARG;
   if (p->storage != MSC_STORAGE_FP64 && p->storage != MSC_STORAGE_FP32 &&
       p->storage != MSC_STORAGE_FP16_DEV)
     return MSC_ERR_INVALID_ARG;

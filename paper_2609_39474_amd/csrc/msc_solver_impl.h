@@ -172,7 +172,8 @@ class Solver : public SolverBase {
           const int n = n_dev + i;
           const int64_t bc = bdf_dev + i;
           const int q = (bc == 0) ? 1 : 2;
-          const int order = (int)std::min<int64_t>(bc, 2);
+          const int max_order = (P.extrap_states == 0) ? 2 : P.extrap_states - 1;
+          const int order = (int)std::min<int64_t>(bc, max_order);
           const double a = (q == 1) ? 1.0 / P.dt : 3.0 / (2.0 * P.dt);
           const int ell0 = (i == 0) ? ell_dev : 1;
           int want;

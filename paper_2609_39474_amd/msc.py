@@ -54,7 +54,7 @@ class msc_params(ctypes.Structure):
         ("corrector", ctypes.c_int32),
         ("storage", ctypes.c_int32),
         ("inputs_on_device", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("extrap_states", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("alloc_fn", ALLOC_FN),
         ("free_fn", FREE_FN),
@@ -301,13 +301,14 @@ class Solver:
 
 
 def make_params(d, N, *, dt, eps, storage="fp64", corrector="shadow", tau_plus=1.0, tau_minus=1.0,
-                k_max=300, n_min=None):
+                k_max=300, n_min=None, extrap_states=0):
     p = msc_params_default(MSC_D2Q9 if d == 2 else MSC_D3Q19, N, dt, eps)
     p.storage = {"fp64": MSC_STORAGE_FP64, "fp32": MSC_STORAGE_FP32, "fp16dev": MSC_STORAGE_FP16_DEV}[storage]
     p.corrector = {"shadow": MSC_CORRECTOR_SHADOW, "picard": MSC_CORRECTOR_PICARD}[corrector]
     p.tau_plus = tau_plus
     p.tau_minus = tau_minus
     p.k_max = k_max
+    p.extrap_states = extrap_states
     if n_min is not None:
         p.n_min = n_min
     return p
