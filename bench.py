@@ -51,6 +51,47 @@ def stokes_decay(u0, t, nu):
     return out
 
 
+def sweep_beyond_cache(msc, stream, torch, NL=4096):
+    """Sweep kernel bandwidth at N = 4096 (two 604 MB FP32 population arrays,
+    beyond the 256 MB last-level cache), explicit and dual-time modes, and a
+    plain device copy of 1.2 GB as the practical ceiling of this GPU."""
+    pz = np.zeros((NL, NL))
+    uz = np.zeros((2, NL, NL))
+    uz[0] = 1e-4 * np.sin(2 * np.pi * np.arange(NL) / NL)[None, :]
+    p = msc.make_params(2, NL, dt=256.0, eps=1e-30, storage="fp32", corrector="picard", k_max=4)
+    big = msc.Solver(p, pz, uz, stream=stream)
+    big.explicit_step(4)
+    big.set_kernel_timing(True)
+    big.explicit_step(20)
+    xs, xn, xb = big.kernel_time(1)
+    big.set_kernel_timing(True)
+    big.bdf2_step(1, raise_on_fail=False)
+    ds, dn, db = big.kernel_time(0)
+    big.close()
+    a = torch.empty(150 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(10):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_s = ev0.elapsed_time(ev1) / 1e3 / 10
+    copy_bytes = 2 * a.numel() * 4
+    del a, b
+    return {
+        "N": NL, "storage": "fp32",
+        "explicit": {"avg_launch_us": xs / xn * 1e6, "bytes_per_launch": xb, "achieved_GBs": xb / (xs / xn) / 1e9,
+                     "frac": xb / (xs / xn) / 1e9 / HBM_PEAK_GBS},
+        "dts": {"avg_launch_us": ds / dn * 1e6, "bytes_per_launch": db, "achieved_GBs": db / (ds / dn) / 1e9,
+                "frac": db / (ds / dn) / 1e9 / HBM_PEAK_GBS, "launches": dn},
+        "device_copy": {"bytes": copy_bytes, "avg_us": copy_s * 1e6, "achieved_GBs": copy_bytes / copy_s / 1e9,
+                        "frac": copy_bytes / copy_s / 1e9 / HBM_PEAK_GBS},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +104,8 @@ def main():
                     help="population states in the initial-trial extrapolation (0: paper rule, up to cubic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the beyond-cache sweep measurement")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the beyond-cache sweep measurement and a plain-copy calibration (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -75,6 +118,10 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
+    if args.sweep_only:
+        r = sweep_beyond_cache(msc, stream, torch)
+        print(json.dumps({"sweep_beyond_cache": r}), flush=True)
+        return
     cfg = W.config(args.workload)
     N, nu, d = cfg["N"], cfg["nu"], cfg["d"]
     shape = (N,) * d
@@ -206,30 +253,10 @@ def main():
 
     # ---- beyond-cache bandwidth: sweep kernel at N = 4096 (2 x 604 MB population arrays)
     if not args.no_large:
-        NL = 4096
-        pz = np.zeros((NL, NL))
-        uz = np.zeros((2, NL, NL))
-        rng = np.random.default_rng(7)
-        uz[0] = 1e-4 * np.sin(2 * np.pi * np.arange(NL) / NL)[None, :] * (1 + 0 * rng.random())
-        p = msc.make_params(2, NL, dt=256.0, eps=1e-30, storage="fp32", corrector="picard", k_max=4)
-        big = msc.Solver(p, pz, uz, stream=stream)
-        big.explicit_step(4)
-        big.set_kernel_timing(True)
-        big.explicit_step(20)
-        xs, xn, xb = big.kernel_time(1)
-        big.set_kernel_timing(True)
-        big.bdf2_step(1, raise_on_fail=False)
-        ds, dn, db = big.kernel_time(0)
-        big.close()
-        out["sweep_beyond_cache"] = {
-            "N": NL, "storage": "fp32",
-            "explicit": {"avg_launch_us": xs / xn * 1e6, "bytes_per_launch": xb, "achieved_GBs": xb / (xs / xn) / 1e9,
-                         "frac": xb / (xs / xn) / 1e9 / HBM_PEAK_GBS},
-            "dts": {"avg_launch_us": ds / dn * 1e6, "bytes_per_launch": db, "achieved_GBs": db / (ds / dn) / 1e9,
-                    "frac": db / (ds / dn) / 1e9 / HBM_PEAK_GBS},
-        }
-        log(f"[bench] N=4096 sweep: explicit {out['sweep_beyond_cache']['explicit']['achieved_GBs']:.0f} GB/s, "
-            f"dts {out['sweep_beyond_cache']['dts']['achieved_GBs']:.0f} GB/s")
+        out["sweep_beyond_cache"] = sweep_beyond_cache(msc, stream, torch)
+        sb = out["sweep_beyond_cache"]
+        log(f"[bench] N=4096 sweep: explicit {sb['explicit']['achieved_GBs']:.0f} GB/s, dts "
+            f"{sb['dts']['achieved_GBs']:.0f} GB/s; device copy {sb['device_copy']['achieved_GBs']:.0f} GB/s")
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:

@@ -210,9 +210,11 @@ msc_status msc_set_kernel_timing(msc_ctx* c, int32_t enable);
 msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* launches,
                            double* bytes_per_launch);
 
-/* Launch-shape knobs for tuning sweeps: key 2 = physical steps enqueued per
+/* Launch-shape knobs for tuning sweeps: key 0 = sweep tile size in sites
+ * (0 = automatic; must match an available tile), key 1 = planes per strip of
+ * the sweep (0 = automatic), key 2 = physical steps enqueued per
  * host synchronisation (>= 1, default 32), 3 = speculative inner iterations
- * enqueued beyond the previous step's count (>= 0, default 1), 4 = capture
+ * enqueued beyond the previous step's count (>= 0, default 0), 4 = capture
  * explicit-march chunks in HIP graphs (0/1, default 1).  Results do not
  * depend on these.  MSC_ERR_INVALID_ARG for an unknown key. */
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);

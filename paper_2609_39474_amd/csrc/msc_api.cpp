@@ -240,11 +240,14 @@ msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
   if (!c) return MSC_ERR_INVALID_ARG;
   msc::Tuning& t = c->s->tuning();
   switch (key) {
+    case 0: t.sweep_tile = value < 0 ? 0 : value; break;
+    case 1: t.sweep_strip = value < 0 ? 0 : value; break;
     case 2: t.batch_steps = value < 1 ? 1 : value; break;
     case 3: t.spec_extra = value < 0 ? 0 : value; break;
     case 4: t.use_graph = value != 0; break;
     default: return MSC_ERR_INVALID_ARG;
   }
+  if (key <= 1) return fwd(c, c->s->reconfigure());
   return MSC_OK;
 }
 

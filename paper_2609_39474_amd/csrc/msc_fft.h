@@ -154,6 +154,7 @@ struct CorrGuard {
 template <class CT, class TM>
 struct Fft2Args {
   CorrGuard g;
+  int do_accept;  // first pass also reconstructs m^{n+1} when step n accepted at ell
   int Nx, Ny, lgx, lgy;
   int NBy;      // N_y/4 + 1
   int rows_per_block, cols_per_block;
@@ -165,8 +166,14 @@ struct Fft2Args {
   double a, nu, inv_ns;
 };
 
-template <class CT, class TM>
-__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A) {
+template <class L, class T, class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A, AcceptArgs<L, T> Ac) {
+  if (A.do_accept && A.g.ctl && phase_accepted(A.g.ctl->phase, A.g.n, A.g.ell)) {
+    // accepted at this sweep: reconstruct m^{n+1} on this block's rows instead
+    const int64_t s0 = (int64_t)blockIdx.x * A.rows_per_block * A.Ny;
+    accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)A.rows_per_block * A.Ny, blockDim.x);
+    return;
+  }
   if (A.g.skip()) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);

@@ -1,148 +1,10 @@
-// Element-wise and control kernels around the sweep: BDF setup and trial
-// extrapolation, the device-side acceptance test of Algorithm 1, the
-// accepted-state reconstruction, initialisation, conversions and the index
-// tables.
+// Element-wise kernels around the sweep: the accepted-state reconstruction,
+// initialisation, conversions and the index tables.
 #pragma once
 
 #include "msc_sweep.h"
 
 namespace msc {
-
-// ---------------------------------------------------------------- setup --
-// Eq. (bdf2): h_1 = m^n/dt, h_2 = (4 m^n - m^{n-1})/(2 dt) in FP64, and the
-// initial trial of the inner solve by population-history extrapolation
-// (Sec. 3.1): f^n, then 2 f^n - f^{n-1}, then 3 f^n - 3 f^{n-1} + f^{n-2}.
-template <class T>
-struct SetupArgs {
-  const DevCtl* ctl;
-  int n;
-  FBufs<T> fb;
-  double* mb[3];
-  double* h;
-  int64_t NS;
-  int D1;      // d + 1
-  int Q;
-  int q;       // BDF order of this step
-  int order;   // extrapolation order 0, 1, 2
-  double dt;
-};
-
-template <class T>
-__global__ void k_setup(SetupArgs<T> A) {
-  using CT = typename CompT<T>::type;
-  const uint64_t ph = A.ctl->phase;
-  if (!phase_ready(ph, A.n, 1)) return;
-  const T* f0 = A.fb.p[A.ctl->slot_hist[0]];
-  const T* f1 = A.fb.p[A.ctl->slot_hist[1]];
-  const T* f2 = A.fb.p[A.ctl->slot_hist[2]];
-  T* tr = A.fb.p[A.ctl->slot_w[0]];
-  const double* mc = A.mb[A.ctl->slot_m[0]];
-  const double* mp = A.mb[A.ctl->slot_m[1]];
-  const int64_t NS = A.NS;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
-    for (int b = 0; b < A.D1; ++b) {
-      const double m0 = mc[b * NS + s];
-      A.h[b * NS + s] = (A.q == 1) ? m0 / A.dt : (4.0 * m0 - mp[b * NS + s]) / (2.0 * A.dt);
-    }
-    for (int k = 0; k < A.Q; ++k) {
-      const int64_t i = (int64_t)k * NS + s;
-      CT v;
-      if (A.order == 0)
-        v = (CT)f0[i];
-      else if (A.order == 1)
-        v = (CT)2 * (CT)f0[i] - (CT)f1[i];
-      else
-        v = (CT)3 * (CT)f0[i] - (CT)3 * (CT)f1[i] + (CT)f2[i];
-      tr[i] = (T)v;
-    }
-  }
-}
-
-// ---------------------------------------------------------- acceptance --
-// One block: FP64 sum of the sweep's block partials in a fixed order, the
-// raw-residual RMS (Eq. residual), and the acceptance test of Algorithm 1:
-// accept when ell >= n_min and the residual is finite and below eps (or at
-// the scheduled count in replay mode); a non-finite residual fails the step
-// (Sec. 4.1); reaching K_max fails it as nonconvergent.  On acceptance the
-// population and moment history slots rotate (Sec. 3.1, last paragraph).
-struct FinishArgs {
-  DevCtl* ctl;
-  int n, ell;
-  const double* partials;
-  int nparts;
-  double inv_count;  // 1/(Q N_sites)
-  double eps;
-  int nmin, kmax, q, mcap;
-  const int32_t* sched;  // accept count of step n at sched[n - stat_base], or null
-  double* Rhist;         // residual history of the current step
-  StepStat* stats;       // stats[n - stat_base]
-  int stat_base;
-};
-
-template <int UNUSED = 0>
-__global__ __launch_bounds__(256) void k_finish(FinishArgs A) {
-  __shared__ double red[256];
-  const uint64_t ph = A.ctl->phase;
-  if (!phase_ready(ph, A.n, A.ell)) return;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < A.nparts; i += 256) acc += A.partials[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double R = sqrt(red[0] * A.inv_count);
-  const int ell = A.ell;
-  A.Rhist[ell - 1] = R;
-  const bool fin = isfinite(R);
-  const bool pass = A.sched ? (ell == A.sched[A.n - A.stat_base]) : (ell >= A.nmin && fin && R < A.eps);
-  DevCtl* c = A.ctl;
-  int fail = 0;
-  if (!pass) {
-    if (!fin)
-      fail = 6;  // MSC_ERR_NONFINITE
-    else if (ell >= A.kmax)
-      fail = 5;  // MSC_ERR_NONCONVERGED
-  }
-  if (pass || fail) {
-    StepStat& st = A.stats[A.n - A.stat_base];
-    st.q = A.q;
-    st.iters = ell;
-    st.R_first = A.Rhist[0];
-    st.R_final = R;
-    double rho = __builtin_nan("");
-    if (ell >= 3) {
-      const int mr = (A.mcap < ell - 1) ? A.mcap : ell - 1;
-      double sl = 0.0;
-      for (int j = ell - mr + 1; j <= ell; ++j) sl += log(A.Rhist[j - 1] / A.Rhist[j - 2]);
-      rho = exp(sl / mr);
-    }
-    st.rho_obs = rho;
-    st.converged = pass ? 1 : 0;
-    st.fail = fail;
-  }
-  if (pass) {
-    const int accb = c->slot_w[ell & 1];
-    const int old2 = c->slot_hist[2];
-    c->slot_hist[2] = c->slot_hist[1];
-    c->slot_hist[1] = c->slot_hist[0];
-    c->slot_hist[0] = accb;
-    c->slot_w[ell & 1] = old2;
-    const int mc = c->slot_m[0], mp = c->slot_m[1], ms = c->slot_m[2];
-    c->slot_m[0] = ms;  // filled with m^{n+1} by k_accept
-    c->slot_m[1] = mc;
-    c->slot_m[2] = mp;
-    c->phase = make_phase(A.n, ell, PH_ACCEPTED);
-  } else if (fail) {
-    c->fail_code = fail;
-    c->phase = make_phase(A.n, ell, PH_FAILED);
-  } else {
-    c->phase = make_phase(A.n, ell, PH_RUNNING);
-  }
-}
 
 // m^{n+1} = R_{q,h}(f_T) with the step's unchanged history (Alg. 1 accept,
 // Eq. macro-reconstruct), from the accepted populations (now f^n slot).
@@ -158,14 +20,11 @@ struct AcceptArgs {
 };
 
 template <class L, class T>
-__global__ void k_accept(AcceptArgs<L, T> A) {
-  const uint64_t ph = A.ctl->phase;
-  if (!phase_accepted(ph, A.n, A.ell)) return;
+__device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64_t s1, int64_t stride) {
   const T* f = A.fb.p[A.ctl->slot_hist[0]];
   double* m = A.mb[A.ctl->slot_m[0]];
   const int64_t NS = A.NS;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
+  for (int64_t s = s0; s < s1; s += stride) {
     double M[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
@@ -178,6 +37,12 @@ __global__ void k_accept(AcceptArgs<L, T> A) {
 #pragma unroll
     for (int b = 0; b <= L::D; ++b) m[b * NS + s] = (M[b] + A.h[b * NS + s] / 2.0) / (1.0 + A.a / 2.0);
   }
+}
+
+template <class L, class T>
+__global__ void k_accept(AcceptArgs<L, T> A) {
+  if (!phase_accepted(A.ctl->phase, A.n, A.ell)) return;
+  accept_sites<L, T>(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, A.NS, (int64_t)gridDim.x * blockDim.x);
 }
 
 // ------------------------------------------------------ initialisation --

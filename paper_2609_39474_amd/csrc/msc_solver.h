@@ -28,7 +28,7 @@ struct Tuning {
   int sweep_tile = 0;     // 0 = automatic
   int sweep_strip = 0;    // planes per strip, 0 = automatic
   int batch_steps = 32;   // physical steps enqueued between host synchronisations
-  int spec_extra = 1;     // speculative iterations beyond the last step's count
+  int spec_extra = 0;     // speculative iterations beyond the last step's count
   int use_graph = 1;      // capture explicit chunks in hipGraphs
 };
 
@@ -53,6 +53,7 @@ class SolverBase {
   virtual msc_status set_kernel_timing(int enable) = 0;
   virtual msc_status kernel_time(int kind, double* seconds, int64_t* launches, double* bytes) = 0;
   virtual Tuning& tuning() = 0;
+  virtual msc_status reconfigure() = 0;  // re-pick launch shapes after a tuning change
 
   std::string last_error;
   bool broken = false;

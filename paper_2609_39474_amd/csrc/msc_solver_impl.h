@@ -59,8 +59,10 @@ void launch_sweep_tile(int mode, const SweepArgs<T, TM>& A, int grid, hipStream_
     hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_EXPLICIT>), dim3(grid), dim3(NT), 0, st, A);
   else if (mode == SW_DTS)
     hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_DTS>), dim3(grid), dim3(NT), 0, st, A);
-  else
+  else if (mode == SW_DTS_LIFT)
     hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_DTS_LIFT>), dim3(grid), dim3(NT), 0, st, A);
+  else
+    hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_DTS_SETUP>), dim3(grid), dim3(NT), 0, st, A);
 }
 
 template <class L, class T, class TM>
@@ -104,6 +106,19 @@ class Solver : public SolverBase {
   ~Solver() override { release(); }
 
   Tuning& tuning() override { return tune; }
+
+  msc_status reconfigure() override {
+    return guard([&]() {
+      sync();
+      choose_sweep();
+      ensure_partials(sweep_grid());
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      if (graph) (void)hipGraphDestroy(graph);
+      gexec = nullptr;
+      graph = nullptr;
+      return MSC_OK;
+    });
+  }
 
   // ----------------------------------------------------------------- init --
   msc_status init(const double* phat0, const double* u0, bool on_device) override {
@@ -183,9 +198,8 @@ class Solver : public SolverBase {
             want = std::max(P.n_min, last_iters + tune.spec_extra);
           int ell1 = (ell0 == 1) ? want : ell0 - 1 + std::max(8, want);
           ell1 = std::min(std::max(ell1, ell0), P.k_max);
-          if (ell0 == 1) enqueue_setup(n, q, order);
           for (int ell = ell0; ell <= ell1; ++ell)
-            enqueue_iteration(n, ell, q, a, use_sched, stat_base);
+            enqueue_iteration(n, ell, q, order, a, use_sched, stat_base);
         }
         MSC_HIPCK(hipMemcpyAsync(ctl_h, ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
         sync();
@@ -353,7 +367,7 @@ class Solver : public SolverBase {
       launch_sweep_timed(SW_DTS, S, 0);
       const double Rv = reduce_partials(S);
       if (R) *R = Rv;
-      enqueue_correction(nullptr, 0, 0, a);
+      enqueue_correction(nullptr, 0, 0, a, nullptr);
       // f_next = f_T + E dm: the same lift the next sweep applies on load,
       // here through an explicit no-op-collision pass is not available, so
       // apply it element-wise.
@@ -765,7 +779,7 @@ class Solver : public SolverBase {
     if (Lp <= 0) {
       int64_t want = (tiles * G.N0) / 512;
       Lp = 1;
-      while (Lp * 2 <= want && Lp < 16) Lp *= 2;
+      while (Lp * 2 <= want && Lp < 64) Lp *= 2;
     }
     Lp = std::min(Lp, G.N0);
     while (G.N0 % Lp) Lp >>= 1;
@@ -801,11 +815,19 @@ class Solver : public SolverBase {
 
   // algorithmic bytes per sweep launch (one read and one write of the
   // populations, plus h, dm in, P r out for the dual-time sweep)
-  double sweep_bytes(int mode) const {
+  // algorithmic HBM bytes of one sweep launch: populations read once per
+  // history state used and written once; h read (or, in setup mode, m^n and
+  // m^{n-1} read and h written); the lift input and P r output
+  double sweep_bytes(int mode, int order = 0, int q = 1) const {
     const double NS = (double)G.NS;
-    double b = 2.0 * Q * sizeof(T) * NS;
-    if (mode != SW_EXPLICIT) b += (D + 1) * NS * (sizeof(double) + sizeof(TM));
-    if (mode == SW_DTS_LIFT) b += (D + 1) * NS * sizeof(TM);
+    const double fb1 = (double)Q * sizeof(T) * NS, mb1 = (double)(D + 1) * NS;
+    if (mode == SW_EXPLICIT) return 2.0 * fb1;
+    double b = 2.0 * fb1 + mb1 * sizeof(TM);  // f in, f_T out, P r out
+    if (mode == SW_DTS_SETUP)
+      b += order * fb1 + mb1 * sizeof(double) * (q == 2 ? 3.0 : 2.0);
+    else
+      b += mb1 * sizeof(double);
+    if (mode == SW_DTS_LIFT) b += mb1 * sizeof(TM);
     return b;
   }
 
@@ -853,7 +875,7 @@ class Solver : public SolverBase {
       ep.b = get_event();
       ep.kind = (mode == SW_EXPLICIT) ? 1 : 0;
       ep.flag = (int)ev_live.size();
-      ep.bytes = sweep_bytes(mode);
+      ep.bytes = sweep_bytes(mode, S.order, S.q);
       S.did_run = run_flags + ep.flag;
       MSC_HIPCK(hipEventRecord(ep.a, st));
     }
@@ -895,37 +917,23 @@ class Solver : public SolverBase {
   }
 
   // --------------------------------------------------- Algorithm 1 pieces --
-  void enqueue_setup(int n, int q, int order) {
-    SetupArgs<T> A{};
-    A.ctl = ctl;
-    A.n = n;
-    A.fb = fb;
-    for (int i = 0; i < 3; ++i) A.mb[i] = mb[i];
-    A.h = h;
-    A.NS = G.NS;
-    A.D1 = D + 1;
-    A.Q = Q;
-    A.q = q;
-    A.order = order;
-    A.dt = P.dt;
-    hipLaunchKernelGGL((k_setup<T>), dim3(ew_grid()), dim3(256), 0, st, A);
-    MSC_HIPCK(hipGetLastError());
-  }
-
-  void enqueue_iteration(int n, int ell, int q, double a, bool use_sched, int stat_base) {
+  // One inner iteration of Algorithm 1 for (step n, sweep ell), guarded on the
+  // device: the sweep (the first one of a step also forms h_q and the
+  // extrapolated trial), the one-block acceptance test, then either the
+  // reconstruction of m^{n+1} (accepted) or the shadow correction.
+  void enqueue_iteration(int n, int ell, int q, int order, double a, bool use_sched, int stat_base) {
     SweepArgs<T, TM> S = sweep_args(a);
     S.ctl = ctl;
     S.n = n;
     S.ell = ell;
-    const bool lift = (ell > 1) && (P.corrector == MSC_CORRECTOR_SHADOW);
-    launch_sweep_timed(lift ? SW_DTS_LIFT : SW_DTS, S, 0);
-
+    for (int i = 0; i < 3; ++i) S.mb[i] = mb[i];
+    S.q = q;
+    S.order = order;
+    S.dt = P.dt;
     FinishArgs F{};
     F.ctl = ctl;
     F.n = n;
     F.ell = ell;
-    F.partials = partials;
-    F.nparts = sweep_grid();
     F.inv_count = 1.0 / ((double)Q * (double)G.NS);
     F.eps = P.eps;
     F.nmin = P.n_min;
@@ -936,9 +944,25 @@ class Solver : public SolverBase {
     F.Rhist = Rhist;
     F.stats = stats_d;
     F.stat_base = stat_base;
-    hipLaunchKernelGGL(k_finish<0>, dim3(1), dim3(256), 0, st, F);
+    int mode;
+    if (ell == 1)
+      mode = SW_DTS_SETUP;
+    else
+      mode = (P.corrector == MSC_CORRECTOR_SHADOW) ? SW_DTS_LIFT : SW_DTS;
+    launch_sweep_timed(mode, S, 0);
+    hipLaunchKernelGGL(k_finish<0>, dim3(1), dim3(256), 0, st, F, (const double*)partials, sweep_grid());
     MSC_HIPCK(hipGetLastError());
 
+    AcceptArgs<L, T> Ac = accept_args(n, ell, a);
+    if (P.corrector == MSC_CORRECTOR_SHADOW) {
+      enqueue_correction(ctl, n, ell, a, &Ac);
+    } else {
+      hipLaunchKernelGGL((k_accept<L, T>), dim3(ew_grid()), dim3(256), 0, st, Ac);
+      MSC_HIPCK(hipGetLastError());
+    }
+  }
+
+  AcceptArgs<L, T> accept_args(int n, int ell, double a) {
     AcceptArgs<L, T> Ac{};
     Ac.ctl = ctl;
     Ac.n = n;
@@ -948,31 +972,35 @@ class Solver : public SolverBase {
     Ac.h = h;
     Ac.NS = G.NS;
     Ac.a = a;
-    hipLaunchKernelGGL((k_accept<L, T>), dim3(ew_grid()), dim3(256), 0, st, Ac);
-    MSC_HIPCK(hipGetLastError());
-
-    if (P.corrector == MSC_CORRECTOR_SHADOW) enqueue_correction(ctl, n, ell, a);
+    return Ac;
   }
 
   // FFT launch shapes
+  // rows per block of the row passes: LDS-limited, and small enough that the
+  // grid has >= 128 blocks when the grid is large enough
   int fft_rows_per_block() const {
     const size_t c = sizeof(cpx<CT>);
     int R = (int)std::max<size_t>(1, (size_t)65536 / (4 * G.N2 * c));
     int p = 1;
     while (p * 2 <= R) p *= 2;
+    while (p > 1 && G.N0 / p < 128) p >>= 1;
     return std::min(p, G.N0);
   }
+  // columns per block of the column pass: LDS-limited, >= 64 blocks if possible
   int fft_cols_per_block() const {
     const size_t c = sizeof(cpx<CT>);
     int J = (int)std::max<size_t>(1, (size_t)98304 / (6 * G.N0 * c));
-    return std::min(J, 16);
+    J = std::min(J, 16);
+    const int NB = G.N2 / 4 + 1;
+    while (J > 1 && (NB + J - 1) / J < 64) J >>= 1;
+    return std::max(J, 1);
   }
 
   void set_fft_attrs() {
     const size_t c = sizeof(cpx<CT>);
     const int rows_b = (int)(4 * fft_rows_per_block() * G.N2 * c);
     const int cols_b = (int)(6 * fft_cols_per_block() * G.N0 * c);
-    MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_fwd<CT, TM>,
+    MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_fwd<L, T, CT, TM>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
     MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_inv<CT, TM>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
@@ -980,9 +1008,11 @@ class Solver : public SolverBase {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, cols_b));
   }
 
-  void enqueue_correction(const DevCtl* c, int n, int ell, double a) {
+  void enqueue_correction(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac) {
     Fft2Args<CT, TM> F{};
     F.g = CorrGuard{c, n, ell};
+    F.do_accept = Ac ? 1 : 0;
+    AcceptArgs<L, T> none{};
     F.Nx = G.N0;
     F.Ny = G.N2;
     F.lgx = ilog2(G.N0);
@@ -1003,7 +1033,7 @@ class Solver : public SolverBase {
     const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
     const int grows = G.N0 / F.rows_per_block;
     const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
-    hipLaunchKernelGGL((k_fft2_rows_fwd<CT, TM>), dim3(grows), dim3(256), rows_b, st, F);
+    hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CT, TM>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none);
     MSC_HIPCK(hipGetLastError());
     hipLaunchKernelGGL((k_fft2_cols_solve<CT, TM>), dim3(gcols), dim3(256), cols_b, st, F);
     MSC_HIPCK(hipGetLastError());

@@ -25,7 +25,11 @@
 
 namespace msc {
 
-enum { SW_EXPLICIT = 0, SW_DTS = 1, SW_DTS_LIFT = 2 };
+// Sweep modes: the source-free explicit map; the dual-time sweep on a given
+// trial; the same with the previous correction's lift fused into the load;
+// and the first sweep of a physical step, which also forms the BDF history
+// term h_q (Eq. bdf2) and the extrapolated trial (Sec. 3.1) while loading.
+enum { SW_EXPLICIT = 0, SW_DTS = 1, SW_DTS_LIFT = 2, SW_DTS_SETUP = 3 };
 
 template <class T>
 struct CompT;
@@ -37,6 +41,78 @@ template <>
 struct CompT<float> {
   using type = float;
 };
+
+// Acceptance test of Algorithm 1, run by one thread once the global sum of
+// r^2 is known.
+struct FinishArgs {
+  DevCtl* ctl;
+  int n, ell;
+  double inv_count;  // 1/(Q N_sites)
+  double eps;
+  int nmin, kmax, q, mcap;
+  const int32_t* sched;  // accept count of step n at sched[n - stat_base], or null
+  double* Rhist;         // residual history of the current step
+  StepStat* stats;       // stats[n - stat_base]
+  int stat_base;
+};
+
+// Raw residual RMS (Eq. residual) and the acceptance decision: accept when
+// ell >= n_min and the residual is finite and below eps (or at the scheduled
+// count in replay mode); a non-finite residual fails the step (Sec. 4.1);
+// reaching K_max fails it as nonconvergent.  On acceptance the population and
+// moment history slots rotate (Sec. 3.1, last paragraph); the moment slot
+// that becomes m^{n+1} is filled by the reconstruction kernel that follows.
+__device__ inline void finish_accept(const FinishArgs& A, double sum_r2) {
+  const double R = sqrt(sum_r2 * A.inv_count);
+  const int ell = A.ell;
+  A.Rhist[ell - 1] = R;
+  const bool fin = isfinite(R);
+  const bool pass = A.sched ? (ell == A.sched[A.n - A.stat_base]) : (ell >= A.nmin && fin && R < A.eps);
+  DevCtl* c = A.ctl;
+  int fail = 0;
+  if (!pass) {
+    if (!fin)
+      fail = 6;  // MSC_ERR_NONFINITE
+    else if (ell >= A.kmax)
+      fail = 5;  // MSC_ERR_NONCONVERGED
+  }
+  if (pass || fail) {
+    StepStat& st = A.stats[A.n - A.stat_base];
+    st.q = A.q;
+    st.iters = ell;
+    st.R_first = A.Rhist[0];
+    st.R_final = R;
+    double rho = __builtin_nan("");
+    if (ell >= 3) {
+      // Eq. (rho-observed): tail geometric mean over m_rho = min(mcap, ell-1)
+      const int mr = (A.mcap < ell - 1) ? A.mcap : ell - 1;
+      double sl = 0.0;
+      for (int j = ell - mr + 1; j <= ell; ++j) sl += log(A.Rhist[j - 1] / A.Rhist[j - 2]);
+      rho = exp(sl / mr);
+    }
+    st.rho_obs = rho;
+    st.converged = pass ? 1 : 0;
+    st.fail = fail;
+  }
+  if (pass) {
+    const int accb = c->slot_w[ell & 1];
+    const int old2 = c->slot_hist[2];
+    c->slot_hist[2] = c->slot_hist[1];
+    c->slot_hist[1] = c->slot_hist[0];
+    c->slot_hist[0] = accb;
+    c->slot_w[ell & 1] = old2;
+    const int mc = c->slot_m[0], mp = c->slot_m[1], ms = c->slot_m[2];
+    c->slot_m[0] = ms;  // becomes m^{n+1}
+    c->slot_m[1] = mc;
+    c->slot_m[2] = mp;
+    c->phase = make_phase(A.n, ell, PH_ACCEPTED);
+  } else if (fail) {
+    c->fail_code = fail;
+    c->phase = make_phase(A.n, ell, PH_FAILED);
+  } else {
+    c->phase = make_phase(A.n, ell, PH_RUNNING);
+  }
+}
 
 template <class T, class TM>
 struct SweepArgs {
@@ -50,13 +126,18 @@ struct SweepArgs {
   FBufs<T> fb;
   const T* src;  // used when ctl == nullptr
   T* dst;
-  const double* h;  // (d+1) x NS, FP64 BDF history term h_q
+  double* h;        // (d+1) x NS FP64 history term h_q: read, or written in setup mode
   const TM* dm;     // (d+1) x NS, previous shadow correction
   TM* Pr;           // (d+1) x NS, residual moments out
   double* partials; // one FP64 partial sum of r^2 per block
   double a, inv1pa2;  // a_q and 1/(1 + a_q/2)
   double wp, wm;      // omega+, omega-
   int* did_run;       // optional: set to 1 when the launch passed its guard
+  // setup mode: moment buffers (roles from control slots), BDF order,
+  // extrapolation order, physical step
+  double* mb[3];
+  int q, order;
+  double dt;
 };
 
 // ---- compile-time direction classification -----------------------------
@@ -100,28 +181,104 @@ __device__ inline int wrapi(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-// Load the trial populations of one site (with the fused lift), reconstruct
-// (Eq. macro-reconstruct), form the source (Eq. source-moments) and collide
-// (Eq. collision with Eq. feq and Eq. source-distribution).
+// Source pointers of one launch, resolved once per block.
+template <class T>
+struct SrcPtrs {
+  const T* s0;  // trial populations (f^n in setup mode)
+  const T* s1;  // f^{n-1} (setup mode)
+  const T* s2;  // f^{n-2} (setup mode)
+  const double* mc;  // m^n (setup mode)
+  const double* mp;  // m^{n-1} (setup mode)
+};
+
+// Raw loads of one site, issued one plane ahead of their use so that the
+// memory latency overlaps the previous plane's collision.
 template <class L, class T, class TM, int MODE>
-__device__ __forceinline__ void load_collide(const SweepArgs<T, TM>& A, const T* __restrict__ src,
-                                             int64_t site, typename CompT<T>::type* f,
-                                             typename CompT<T>::type* C) {
-  using CT = typename CompT<T>::type;
+struct RawSite {
+  static constexpr int Q = L::Q, D1 = L::D + 1;
+  T f0[Q];
+  T f1[MODE == SW_DTS_SETUP ? Q : 1];
+  T f2[MODE == SW_DTS_SETUP ? Q : 1];
+  TM dmv[MODE == SW_DTS_LIFT ? D1 : 1];
+  double hv[MODE == SW_EXPLICIT ? 1 : D1];  // h, or m^n in setup mode
+  double mpv[MODE == SW_DTS_SETUP ? D1 : 1];
+};
+
+template <class L, class T, class TM, int MODE>
+__device__ __forceinline__ void load_raw(const SweepArgs<T, TM>& A, const SrcPtrs<T>& P, int64_t site,
+                                         RawSite<L, T, TM, MODE>& r) {
   constexpr int Q = L::Q, D = L::D;
   const int64_t NS = A.NS;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) f[k] = (CT)src[k * NS + site];
-  if (MODE == SW_DTS_LIFT) {
-    CT d0 = (CT)A.dm[site];
-    CT du[3] = {0, 0, 0};
+  for (int k = 0; k < Q; ++k) r.f0[k] = P.s0[k * NS + site];
+  if (MODE == SW_DTS_SETUP) {
+    if (A.order >= 1) {
 #pragma unroll
-    for (int b = 0; b < D; ++b) du[b] = (CT)A.dm[(1 + b) * NS + site];
+      for (int k = 0; k < Q; ++k) r.f1[k] = P.s1[k * NS + site];
+    }
+    if (A.order >= 2) {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) r.f2[k] = P.s2[k * NS + site];
+    }
+#pragma unroll
+    for (int b = 0; b <= D; ++b) r.hv[b] = P.mc[b * NS + site];
+    if (A.q == 2) {
+#pragma unroll
+      for (int b = 0; b <= D; ++b) r.mpv[b] = P.mp[b * NS + site];
+    }
+  } else if (MODE != SW_EXPLICIT) {
+#pragma unroll
+    for (int b = 0; b <= D; ++b) r.hv[b] = A.h[b * NS + site];
+  }
+  if (MODE == SW_DTS_LIFT) {
+#pragma unroll
+    for (int b = 0; b <= D; ++b) r.dmv[b] = A.dm[b * NS + site];
+  }
+}
+
+// From the raw loads: the trial populations (extrapolated in setup mode, with
+// the lift of Eq. lift added in lift mode), then reconstruct (Eq.
+// macro-reconstruct), form the source (Eq. source-moments) and collide (Eq.
+// collision with Eq. feq and Eq. source-distribution).  hout receives h_q
+// (setup mode).
+template <class L, class T, class TM, int MODE>
+__device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const RawSite<L, T, TM, MODE>& r,
+                                            typename CompT<T>::type* f, typename CompT<T>::type* C,
+                                            double* hout) {
+  using CT = typename CompT<T>::type;
+  constexpr int Q = L::Q, D = L::D;
+  double h[4] = {0, 0, 0, 0};
+  if (MODE == SW_DTS_SETUP) {
+    // Eq. (bdf2) in FP64, and the extrapolated initial trial (Sec. 3.1)
+#pragma unroll
+    for (int b = 0; b <= D; ++b)
+      h[b] = (A.q == 1) ? r.hv[b] / A.dt : (4.0 * r.hv[b] - r.mpv[b]) / (2.0 * A.dt);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (A.order == 0)
+        f[k] = (CT)r.f0[k];
+      else if (A.order == 1)
+        f[k] = (CT)2 * (CT)r.f0[k] - (CT)r.f1[k];
+      else
+        f[k] = (CT)3 * (CT)r.f0[k] - (CT)3 * (CT)r.f1[k] + (CT)r.f2[k];
+    }
+#pragma unroll
+    for (int b = 0; b <= D; ++b) hout[b] = h[b];
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f[k] = (CT)r.f0[k];
+    if (MODE != SW_EXPLICIT) {
+#pragma unroll
+      for (int b = 0; b <= D; ++b) h[b] = r.hv[b];
+    }
+  }
+  if (MODE == SW_DTS_LIFT) {
+    const CT d0 = (CT)r.dmv[0];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       CT cu = 0;
 #pragma unroll
-      for (int b = 0; b < D; ++b) cu += (CT)ca<L>(k, b) * du[b];
+      for (int b = 0; b < D; ++b) cu += (CT)ca<L>(k, b) * (CT)r.dmv[1 + b];
       f[k] += (CT)L::w(k) * (d0 + (CT)3 * cu);
     }
   }
@@ -145,10 +302,9 @@ __device__ __forceinline__ void load_collide(const SweepArgs<T, TM>& A, const T*
     // two O(m/dt) terms.
 #pragma unroll
     for (int b = 0; b <= D; ++b) {
-      double hb = A.h[b * NS + site];
-      double mb = ((double)M[b] + 0.5 * hb) * A.inv1pa2;
+      const double mb = ((double)M[b] + 0.5 * h[b]) * A.inv1pa2;
       m[b] = (CT)mb;
-      s[b] = (CT)(hb - A.a * mb);
+      s[b] = (CT)(h[b] - A.a * mb);
     }
   }
   const CT uu = m[1] * m[1] + m[2] * m[2] + (D == 3 ? m[3] * m[3] : (CT)0);
@@ -200,14 +356,22 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
   __shared__ T ldsP[4][NGP][NI];
   __shared__ T ldsZ[3][NG0][NI];
   __shared__ T ldsM[2][NGM][NI];
-  __shared__ double red[NT / 64 + 1];
+  __shared__ double red[NT];
 
-  const T* __restrict__ src = A.src;
+  SrcPtrs<T> P{A.src, nullptr, nullptr, nullptr, nullptr};
   T* __restrict__ dst = A.dst;
   if (A.ctl) {
     const uint64_t ph = A.ctl->phase;
     if (!phase_ready(ph, A.n, A.ell)) return;  // uniform for the grid
-    src = A.fb.p[A.ctl->slot_w[(A.ell - 1) & 1]];
+    if (MODE == SW_DTS_SETUP) {
+      P.s0 = A.fb.p[A.ctl->slot_hist[0]];
+      P.s1 = A.fb.p[A.ctl->slot_hist[1]];
+      P.s2 = A.fb.p[A.ctl->slot_hist[2]];
+      P.mc = A.mb[A.ctl->slot_m[0]];
+      P.mp = A.mb[A.ctl->slot_m[1]];
+    } else {
+      P.s0 = A.fb.p[A.ctl->slot_w[(A.ell - 1) & 1]];
+    }
     dst = A.fb.p[A.ctl->slot_w[A.ell & 1]];
   }
   if (A.did_run && blockIdx.x == 0 && threadIdx.x == 0) *A.did_run = 1;
@@ -231,7 +395,19 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
 
   CT fprev[SPT][Q], fcur[SPT][Q];
   CT c0prev[SPT], cpx1[SPT], cpx2[SPT], cmxc[SPT], c0c[SPT], cpxc[SPT];
+  RawSite<L, T, TM, MODE> raw[SPT];
   double r2 = 0.0;
+
+  // prefetch the owned sites of the first source plane
+  {
+    const int xs0 = wrapi(x0 - 1, N0);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int s = tid + j * NT;
+      const int i1 = s / T2, i2 = s - (s / T2) * T2;
+      load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs0 * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
+    }
+  }
 
   for (int it = 0; it < A.L + 2; ++it) {
     const int xs = wrapi(x0 - 1 + it, N0);
@@ -240,14 +416,24 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
     const bool wM = it >= 2;                   // dest plane it-1
     const int sP = (it + 1) & 3, sZ = it % 3, sM = (it + 1) & 1;
 
-    // ---- owned interior sources ------------------------------------------
+    // ---- owned interior sources --------------------------------------------
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
       const int s = tid + j * NT;
       const int i1 = s / T2, i2 = s - (s / T2) * T2;
-      const int64_t site = ((int64_t)xs * N1 + (b1 + i1)) * N2 + (b2 + i2);
+      RawSite<L, T, TM, MODE> cur = raw[j];
+      if (it + 1 < A.L + 2) {
+        const int xn = wrapi(x0 + it, N0);
+        load_raw<L, T, TM, MODE>(A, P, ((int64_t)xn * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
+      }
       CT C[Q];
-      load_collide<L, T, TM, MODE>(A, src, site, fcur[j], C);
+      double hs[4];
+      collide_raw<L, T, TM, MODE>(A, cur, fcur[j], C, hs);
+      if (MODE == SW_DTS_SETUP && it >= 1 && it <= A.L) {
+        const int64_t site = ((int64_t)xs * N1 + (b1 + i1)) * N2 + (b2 + i2);
+#pragma unroll
+        for (int bb = 0; bb <= D; ++bb) A.h[bb * NS + site] = hs[bb];
+      }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (is_local<L>(k)) continue;
@@ -282,9 +468,11 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
         i1 = u % T1;
       }
       const int p1 = wrapi(b1 + i1, N1), p2 = wrapi(b2 + i2, N2);
-      const int64_t site = ((int64_t)xs * N1 + p1) * N2 + p2;
+      RawSite<L, T, TM, MODE> hr;
+      load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs * N1 + p1) * N2 + p2, hr);
       CT f[Q], C[Q];
-      load_collide<L, T, TM, MODE>(A, src, site, f, C);
+      double hs[4];
+      collide_raw<L, T, TM, MODE>(A, hr, f, C, hs);
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (is_local<L>(k)) continue;
@@ -330,7 +518,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
             const int g = xgroup<L>(k), gi = group_index<L>(k);
             v = (g == 0) ? (CT)ldsP[rP][gi][s] : ((g == 1) ? (CT)ldsZ[rZ][gi][s] : (CT)ldsM[rM][gi][s]);
           }
-          dst[k * NS + site] = (T)v;
+          __builtin_nontemporal_store((T)v, &dst[k * NS + site]);
           if (MODE != SW_EXPLICIT) {
             const CT r = v - fprev[j][k];
             pr[0] += r;
@@ -342,7 +530,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
         }
         if (MODE != SW_EXPLICIT) {
 #pragma unroll
-          for (int bb = 0; bb <= D; ++bb) A.Pr[bb * NS + site] = (TM)pr[bb];
+          for (int bb = 0; bb <= D; ++bb) __builtin_nontemporal_store((TM)pr[bb], &A.Pr[bb * NS + site]);
         }
       }
     }
@@ -358,30 +546,44 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
   }
 
   if (MODE != SW_EXPLICIT) {
-    // FP64 block reduction of sum r^2: wave shuffles, then LDS across waves.
+    // FP64 block reduction of sum r^2 (wave shuffles, then LDS across waves;
+    // blocks narrower than a wavefront sum serially).
+    double acc = 0.0;
     if (NT >= 64) {
       double v = r2;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
       if ((tid & 63) == 0) red[tid >> 6] = v;
       __syncthreads();
-      if (tid == 0) {
-        double acc = 0.0;
+      if (tid == 0)
         for (int wv = 0; wv < NT / 64; ++wv) acc += red[wv];
-        A.partials[blockIdx.x] = acc;
-      }
     } else {
-      // blocks narrower than a wavefront (tiny test grids): serial sum
-      __shared__ double reds[NT];
-      reds[tid] = r2;
+      red[tid] = r2;
       __syncthreads();
-      if (tid == 0) {
-        double acc = 0.0;
-        for (int i = 0; i < NT; ++i) acc += reds[i];
-        A.partials[blockIdx.x] = acc;
-      }
+      if (tid == 0)
+        for (int i = 0; i < NT; ++i) acc += red[i];
     }
+    if (tid == 0) A.partials[blockIdx.x] = acc;
   }
+}
+
+// One block: FP64 sum of the sweep's block partials in a fixed order, then
+// the acceptance test.  A separate launch, so the partials written by blocks
+// on every XCD are visible through the kernel boundary (a per-block
+// agent-scope fence would write back the L2 after every block).
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_finish(FinishArgs A, const double* __restrict__ partials, int nparts) {
+  __shared__ double red[256];
+  if (!phase_ready(A.ctl->phase, A.n, A.ell)) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) acc += partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) finish_accept(A, red[0]);
 }
 
 }  // namespace msc
