@@ -310,4 +310,221 @@ __global__ __launch_bounds__(256) void k_fft2_rows_inv(Fft2Args<CT, TM> A) {
   }
 }
 
+// ---------------------------------------------------------------- 3D ----
+// Five passes over the band |j_alpha| <= N_alpha/4: forward along z (real
+// input, keeps j_z = 0..N_z/4), forward along y (keeps the y band), along x
+// with the FP64 4x4 Schur solve of Eq. (schur) between the forward and
+// inverse transforms, inverse along y, inverse along z to real fields.
+// spec1 holds [field][x][y][j_z] (after the z passes), spec2 holds
+// [field][x][band_y][j_z] (after the y passes).
+template <class CT, class TM>
+struct Fft3Args {
+  CorrGuard g;
+  int do_accept;
+  int Nx, Ny, Nz, lgx, lgy, lgz;
+  int NBz;  // N_z/4 + 1
+  int NBy;  // 2 (N_y/4) + 1 retained y indices
+  int pencils_per_block, cols_per_block;
+  const TM* Pr;        // 4 x N_sites
+  TM* dm;              // 4 x N_sites
+  cpx<CT>* spec1;      // 4 x Nx*Ny x NBz
+  cpx<CT>* spec2;      // 4 x Nx*NBy x NBz
+  const cpx<CT>* twx;
+  const cpx<CT>* twy;
+  const cpx<CT>* twz;
+  double a, nu, inv_ns;
+};
+
+__device__ inline int band_to_j(int i, int N, int NB) { return (i <= N / 4) ? i : N - (NB - i); }
+
+// pass 1: forward along z of pencils (x, y); fields (0,1) and (2,3) packed
+template <class L, class T, class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft3_z_fwd(Fft3Args<CT, TM> A, AcceptArgs<L, T> Ac) {
+  const int R = A.pencils_per_block, Nz = A.Nz;
+  if (A.do_accept && A.g.ctl && phase_accepted(A.g.ctl->phase, A.g.n, A.g.ell)) {
+    const int64_t s0 = (int64_t)blockIdx.x * R * Nz;
+    accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)R * Nz, blockDim.x);
+    return;
+  }
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  cpx<CT>* tmp = buf + 2 * R * Nz;
+  const int64_t p0 = (int64_t)blockIdx.x * R;
+  const int64_t NS = (int64_t)A.Nx * A.Ny * Nz;
+  for (int i = threadIdx.x; i < R * Nz; i += blockDim.x) {
+    const int r = i / Nz, z = i - r * Nz;
+    const int64_t s = (p0 + r) * Nz + z;
+    buf[(2 * r) * Nz + z] = {(CT)A.Pr[s], (CT)A.Pr[NS + s]};
+    buf[(2 * r + 1) * Nz + z] = {(CT)A.Pr[2 * NS + s], (CT)A.Pr[3 * NS + s]};
+  }
+  __syncthreads();
+  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgz, 2 * R, -1, A.twz);
+  const int NB = A.NBz;
+  const int64_t FS = (int64_t)A.Nx * A.Ny * NB;
+  for (int i = threadIdx.x; i < R * NB; i += blockDim.x) {
+    const int r = i / NB, j = i - r * NB;
+    const int64_t o = (p0 + r) * NB + j;
+    for (int h = 0; h < 2; ++h) {
+      const cpx<CT> z = out[(2 * r + h) * Nz + j];
+      const cpx<CT> zc = out[(2 * r + h) * Nz + ((Nz - j) & (Nz - 1))];
+      A.spec1[(2 * h) * FS + o] = {(CT)0.5 * (z.x + zc.x), (CT)0.5 * (z.y - zc.y)};
+      A.spec1[(2 * h + 1) * FS + o] = {(CT)0.5 * (z.y + zc.y), (CT)0.5 * (zc.x - z.x)};
+    }
+  }
+}
+
+// pass 2: forward along y for a group of j_z columns at one x; keep the band
+template <class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft3_y_fwd(Fft3Args<CT, TM> A) {
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int Ny = A.Ny, JB = A.cols_per_block, NBz = A.NBz;
+  cpx<CT>* tmp = buf + 4 * JB * Ny;
+  const int ngroups = (NBz + JB - 1) / JB;
+  const int x = blockIdx.x / ngroups, j0 = (blockIdx.x % ngroups) * JB;
+  const int64_t FS1 = (int64_t)A.Nx * Ny * NBz, FS2 = (int64_t)A.Nx * A.NBy * NBz;
+  for (int i = threadIdx.x; i < 4 * JB * Ny; i += blockDim.x) {
+    const int c = i % JB, rest = i / JB;
+    const int y = rest % Ny, f = rest / Ny;
+    const int j = j0 + c;
+    buf[(f * JB + c) * Ny + y] = (j < NBz) ? A.spec1[f * FS1 + ((int64_t)x * Ny + y) * NBz + j] : cpx<CT>{0, 0};
+  }
+  __syncthreads();
+  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgy, 4 * JB, -1, A.twy);
+  for (int i = threadIdx.x; i < 4 * JB * A.NBy; i += blockDim.x) {
+    const int c = i % JB, rest = i / JB;
+    const int bi = rest % A.NBy, f = rest / A.NBy;
+    const int j = j0 + c;
+    if (j < NBz)
+      A.spec2[f * FS2 + ((int64_t)x * A.NBy + bi) * NBz + j] = out[(f * JB + c) * Ny + band_to_j(bi, Ny, A.NBy)];
+  }
+}
+
+// pass 3: along x for a group of j_z columns at one band-y index: forward,
+// FP64 Schur solve on |j_x| <= N_x/4 (zero elsewhere), inverse; in place
+template <class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft3_x_solve(Fft3Args<CT, TM> A) {
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int Nx = A.Nx, JB = A.cols_per_block, NBz = A.NBz, NBy = A.NBy;
+  cpx<CT>* tmp = buf + 4 * JB * Nx;
+  const int ngroups = (NBz + JB - 1) / JB;
+  const int bi = blockIdx.x / ngroups, j0 = (blockIdx.x % ngroups) * JB;
+  const int64_t FS2 = (int64_t)Nx * NBy * NBz;
+  for (int i = threadIdx.x; i < 4 * JB * Nx; i += blockDim.x) {
+    const int c = i % JB, rest = i / JB;
+    const int x = rest % Nx, f = rest / Nx;
+    const int j = j0 + c;
+    buf[(f * JB + c) * Nx + x] = (j < NBz) ? A.spec2[f * FS2 + ((int64_t)x * NBy + bi) * NBz + j] : cpx<CT>{0, 0};
+  }
+  __syncthreads();
+  cpx<CT>* F = lds_fft<CT>(buf, tmp, A.lgx, 4 * JB, -1, A.twx);
+  cpx<CT>* Gb = (F == buf) ? tmp : buf;
+  const double two_pi = 6.283185307179586476925286766559;
+  const int sjy = signed_index(band_to_j(bi, A.Ny, NBy), A.Ny);
+  for (int i = threadIdx.x; i < JB * Nx; i += blockDim.x) {
+    const int c = i / Nx, jx = i - c * Nx;
+    const int jz = j0 + c;
+    const int sjx = signed_index(jx, Nx);
+    if (jz < NBz && in_band(sjx, Nx)) {
+      double kv[3] = {two_pi * sjx / Nx, two_pi * sjy / A.Ny, two_pi * jz / A.Nz};
+      double r[4][2], o[4][2];
+      for (int f = 0; f < 4; ++f) {
+        const cpx<CT> v = F[(f * JB + c) * Nx + jx];
+        r[f][0] = (double)v.x;
+        r[f][1] = (double)v.y;
+      }
+      schur_solve<3>(kv, r, A.a, A.nu, A.inv_ns, o);
+      for (int f = 0; f < 4; ++f) Gb[(f * JB + c) * Nx + jx] = {(CT)o[f][0], (CT)o[f][1]};
+    } else {
+      for (int f = 0; f < 4; ++f) Gb[(f * JB + c) * Nx + jx] = {(CT)0, (CT)0};
+    }
+  }
+  __syncthreads();
+  cpx<CT>* H = lds_fft<CT>(Gb, F, A.lgx, 4 * JB, +1, A.twx);
+  for (int i = threadIdx.x; i < 4 * JB * Nx; i += blockDim.x) {
+    const int c = i % JB, rest = i / JB;
+    const int x = rest % Nx, f = rest / Nx;
+    const int j = j0 + c;
+    if (j < NBz) A.spec2[f * FS2 + ((int64_t)x * NBy + bi) * NBz + j] = H[(f * JB + c) * Nx + x];
+  }
+}
+
+// pass 4: inverse along y from the band to every y, for a group of j_z at x
+template <class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft3_y_inv(Fft3Args<CT, TM> A) {
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int Ny = A.Ny, JB = A.cols_per_block, NBz = A.NBz, NBy = A.NBy;
+  cpx<CT>* tmp = buf + 4 * JB * Ny;
+  const int ngroups = (NBz + JB - 1) / JB;
+  const int x = blockIdx.x / ngroups, j0 = (blockIdx.x % ngroups) * JB;
+  const int64_t FS1 = (int64_t)A.Nx * Ny * NBz, FS2 = (int64_t)A.Nx * NBy * NBz;
+  for (int i = threadIdx.x; i < 4 * JB * Ny; i += blockDim.x) {
+    const int c = i % JB, rest = i / JB;
+    const int jy = rest % Ny, f = rest / Ny;
+    const int j = j0 + c;
+    cpx<CT> v = {0, 0};
+    const int bi = (jy <= Ny / 4) ? jy : ((Ny - jy <= Ny / 4) ? NBy - (Ny - jy) : -1);
+    if (j < NBz && bi >= 0) v = A.spec2[f * FS2 + ((int64_t)x * NBy + bi) * NBz + j];
+    buf[(f * JB + c) * Ny + jy] = v;
+  }
+  __syncthreads();
+  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgy, 4 * JB, +1, A.twy);
+  for (int i = threadIdx.x; i < 4 * JB * Ny; i += blockDim.x) {
+    const int c = i % JB, rest = i / JB;
+    const int y = rest % Ny, f = rest / Ny;
+    const int j = j0 + c;
+    if (j < NBz) A.spec1[f * FS1 + ((int64_t)x * Ny + y) * NBz + j] = out[(f * JB + c) * Ny + y];
+  }
+}
+
+// pass 5: inverse along z from j_z = 0..N_z/4 (conjugate-symmetric
+// extension, real part at j_z = 0) to real fields; (0,1) and (2,3) packed
+template <class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft3_z_inv(Fft3Args<CT, TM> A) {
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int R = A.pencils_per_block, Nz = A.Nz, NB = A.NBz;
+  cpx<CT>* tmp = buf + 2 * R * Nz;
+  const int64_t p0 = (int64_t)blockIdx.x * R;
+  const int64_t FS = (int64_t)A.Nx * A.Ny * NB;
+  for (int i = threadIdx.x; i < R * Nz; i += blockDim.x) {
+    const int r = i / Nz, j = i - r * Nz;
+    const int64_t o = (p0 + r) * NB;
+    cpx<CT> v[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    if (j < NB) {
+      for (int f = 0; f < 4; ++f) {
+        v[f] = A.spec1[f * FS + o + j];
+        if (j == 0) v[f].y = 0;
+      }
+    } else if (Nz - j < NB) {
+      for (int f = 0; f < 4; ++f) {
+        v[f] = A.spec1[f * FS + o + (Nz - j)];
+        v[f].y = -v[f].y;
+      }
+    }
+    buf[(2 * r) * Nz + j] = {v[0].x - v[1].y, v[0].y + v[1].x};
+    buf[(2 * r + 1) * Nz + j] = {v[2].x - v[3].y, v[2].y + v[3].x};
+  }
+  __syncthreads();
+  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgz, 2 * R, +1, A.twz);
+  const int64_t NS = (int64_t)A.Nx * A.Ny * Nz;
+  for (int i = threadIdx.x; i < R * Nz; i += blockDim.x) {
+    const int r = i / Nz, z = i - r * Nz;
+    const int64_t s = (p0 + r) * Nz + z;
+    const cpx<CT> a = out[(2 * r) * Nz + z];
+    const cpx<CT> b = out[(2 * r + 1) * Nz + z];
+    A.dm[s] = (TM)a.x;
+    A.dm[NS + s] = (TM)a.y;
+    A.dm[2 * NS + s] = (TM)b.x;
+    A.dm[3 * NS + s] = (TM)b.y;
+  }
+}
+
 }  // namespace msc

@@ -469,6 +469,7 @@ class Solver : public SolverBase {
   TM* Pr = nullptr;
   TM* dm = nullptr;
   cpx<CT>* spec = nullptr;
+  cpx<CT>* spec2 = nullptr;
   double* partials = nullptr;
   double* partials_h = nullptr;
   int nparts_cap = 0;
@@ -564,12 +565,14 @@ class Solver : public SolverBase {
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 4096);
   }
 
-  bool corrector_supported() const { return D == 2 && fft_fits(); }
+  bool corrector_supported() const { return fft_fits(); }
 
+  // LDS of the transform passes at their minimum block shape
   bool fft_fits() const {
-    if (D != 2) return false;
     const size_t c = sizeof(cpx<CT>);
-    return (size_t)4 * G.N2 * c <= 131072 && (size_t)6 * G.N0 * c <= 131072;
+    if (D == 2) return (size_t)4 * G.N2 * c <= 131072 && (size_t)6 * G.N0 * c <= 131072;
+    const int Nmax = std::max(G.n[0], std::max(G.n[1], G.n[2]));
+    return (size_t)4 * G.n[2] * c <= 131072 && (size_t)8 * Nmax * c <= 131072;
   }
 
   void allocate() {
@@ -588,10 +591,17 @@ class Solver : public SolverBase {
     choose_sweep();
     ensure_partials(sweep_grid());
     if (corrector_supported()) {
-      const int NB = G.N2 / 4 + 1;
-      spec = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * 3 * (int64_t)G.N0 * NB));
-      tw[0] = make_twiddles(G.N0);
-      tw[2] = make_twiddles(G.N2);
+      if (D == 2) {
+        const int NB = G.N2 / 4 + 1;
+        spec = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * 3 * (int64_t)G.N0 * NB));
+        tw[0] = make_twiddles(G.N0);
+        tw[2] = make_twiddles(G.N2);
+      } else {
+        const int NBz = G.n[2] / 4 + 1, NBy = 2 * (G.n[1] / 4) + 1;
+        spec = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * 4 * (int64_t)G.n[0] * G.n[1] * NBz));
+        spec2 = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * 4 * (int64_t)G.n[0] * NBy * NBz));
+        for (int a = 0; a < 3; ++a) tw[a] = make_twiddles(G.n[a]);
+      }
       set_fft_attrs();
     }
   }
@@ -996,49 +1006,129 @@ class Solver : public SolverBase {
     return std::max(J, 1);
   }
 
-  void set_fft_attrs() {
+  // 3D launch shapes: pencils per block of the z passes, j_z columns per
+  // block of the y and x passes
+  int fft3_pencils_per_block() const {
     const size_t c = sizeof(cpx<CT>);
-    const int rows_b = (int)(4 * fft_rows_per_block() * G.N2 * c);
-    const int cols_b = (int)(6 * fft_cols_per_block() * G.N0 * c);
-    MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_fwd<L, T, CT, TM>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
-    MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_inv<CT, TM>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
-    MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_cols_solve<CT, TM>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, cols_b));
+    int R = (int)std::max<size_t>(1, (size_t)65536 / (4 * G.n[2] * c));
+    int p = 1;
+    while (p * 2 <= R) p *= 2;
+    while (p > 1 && ((int64_t)G.n[0] * G.n[1]) / p < 256) p >>= 1;
+    return p;
+  }
+  int fft3_cols_per_block() const {
+    const size_t c = sizeof(cpx<CT>);
+    const int Nmax = std::max(G.n[0], G.n[1]);
+    int J = (int)std::max<size_t>(1, (size_t)98304 / (8 * Nmax * c));
+    J = std::min(J, 8);
+    return std::max(J, 1);
   }
 
+  void set_fft_attrs() {
+    const size_t c = sizeof(cpx<CT>);
+    if constexpr (D == 2) {
+      const int rows_b = (int)(4 * fft_rows_per_block() * G.N2 * c);
+      const int cols_b = (int)(6 * fft_cols_per_block() * G.N0 * c);
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_fwd<L, T, CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_inv<CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_cols_solve<CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, cols_b));
+    } else {
+      const int zb = (int)(4 * fft3_pencils_per_block() * G.n[2] * c);
+      const int Nmax = std::max(G.n[0], G.n[1]);
+      const int cb = (int)(8 * fft3_cols_per_block() * Nmax * c);
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_z_fwd<L, T, CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, zb));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_z_inv<CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, zb));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_y_fwd<CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, cb));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_y_inv<CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, cb));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_x_solve<CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, cb));
+    }
+  }
+
+  // The shadow correction of Eq. (shadow-update) for (step n, sweep ell):
+  // transforms of P r, per-wavevector Schur solve, inverse transforms into dm
+  // (the lift is fused into the next sweep).  With Ac the first pass instead
+  // reconstructs m^{n+1} when the step was accepted at this sweep.
   void enqueue_correction(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac) {
-    Fft2Args<CT, TM> F{};
-    F.g = CorrGuard{c, n, ell};
-    F.do_accept = Ac ? 1 : 0;
     AcceptArgs<L, T> none{};
-    F.Nx = G.N0;
-    F.Ny = G.N2;
-    F.lgx = ilog2(G.N0);
-    F.lgy = ilog2(G.N2);
-    F.NBy = G.N2 / 4 + 1;
-    F.rows_per_block = fft_rows_per_block();
-    F.cols_per_block = fft_cols_per_block();
-    F.Pr = Pr;
-    F.spec = spec;
-    F.dm = dm;
-    F.twx = tw[0];
-    F.twy = tw[2];
-    F.a = a;
-    F.nu = nu;
-    F.inv_ns = 1.0 / (double)G.NS;
     const size_t cb = sizeof(cpx<CT>);
-    const size_t rows_b = 4 * (size_t)F.rows_per_block * G.N2 * cb;
-    const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
-    const int grows = G.N0 / F.rows_per_block;
-    const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
-    hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CT, TM>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none);
-    MSC_HIPCK(hipGetLastError());
-    hipLaunchKernelGGL((k_fft2_cols_solve<CT, TM>), dim3(gcols), dim3(256), cols_b, st, F);
-    MSC_HIPCK(hipGetLastError());
-    hipLaunchKernelGGL((k_fft2_rows_inv<CT, TM>), dim3(grows), dim3(256), rows_b, st, F);
-    MSC_HIPCK(hipGetLastError());
+    if constexpr (D == 2) {
+      Fft2Args<CT, TM> F{};
+      F.g = CorrGuard{c, n, ell};
+      F.do_accept = Ac ? 1 : 0;
+      F.Nx = G.N0;
+      F.Ny = G.N2;
+      F.lgx = ilog2(G.N0);
+      F.lgy = ilog2(G.N2);
+      F.NBy = G.N2 / 4 + 1;
+      F.rows_per_block = fft_rows_per_block();
+      F.cols_per_block = fft_cols_per_block();
+      F.Pr = Pr;
+      F.spec = spec;
+      F.dm = dm;
+      F.twx = tw[0];
+      F.twy = tw[2];
+      F.a = a;
+      F.nu = nu;
+      F.inv_ns = 1.0 / (double)G.NS;
+      const size_t rows_b = 4 * (size_t)F.rows_per_block * G.N2 * cb;
+      const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
+      const int grows = G.N0 / F.rows_per_block;
+      const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
+      hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CT, TM>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none);
+      MSC_HIPCK(hipGetLastError());
+      hipLaunchKernelGGL((k_fft2_cols_solve<CT, TM>), dim3(gcols), dim3(256), cols_b, st, F);
+      MSC_HIPCK(hipGetLastError());
+      hipLaunchKernelGGL((k_fft2_rows_inv<CT, TM>), dim3(grows), dim3(256), rows_b, st, F);
+      MSC_HIPCK(hipGetLastError());
+    } else {
+      Fft3Args<CT, TM> F{};
+      F.g = CorrGuard{c, n, ell};
+      F.do_accept = Ac ? 1 : 0;
+      F.Nx = G.n[0];
+      F.Ny = G.n[1];
+      F.Nz = G.n[2];
+      F.lgx = ilog2(F.Nx);
+      F.lgy = ilog2(F.Ny);
+      F.lgz = ilog2(F.Nz);
+      F.NBz = F.Nz / 4 + 1;
+      F.NBy = 2 * (F.Ny / 4) + 1;
+      F.pencils_per_block = fft3_pencils_per_block();
+      F.cols_per_block = fft3_cols_per_block();
+      F.Pr = Pr;
+      F.dm = dm;
+      F.spec1 = spec;
+      F.spec2 = spec2;
+      F.twx = tw[0];
+      F.twy = tw[1];
+      F.twz = tw[2];
+      F.a = a;
+      F.nu = nu;
+      F.inv_ns = 1.0 / (double)G.NS;
+      const int R = F.pencils_per_block, JB = F.cols_per_block;
+      const size_t zb = 4 * (size_t)R * F.Nz * cb;
+      const size_t yb = 8 * (size_t)JB * F.Ny * cb;
+      const size_t xb = 8 * (size_t)JB * F.Nx * cb;
+      const int ng = (F.NBz + JB - 1) / JB;
+      const int gz = (int)(((int64_t)F.Nx * F.Ny) / R);
+      hipLaunchKernelGGL((k_fft3_z_fwd<L, T, CT, TM>), dim3(gz), dim3(256), zb, st, F, Ac ? *Ac : none);
+      MSC_HIPCK(hipGetLastError());
+      hipLaunchKernelGGL((k_fft3_y_fwd<CT, TM>), dim3(F.Nx * ng), dim3(256), yb, st, F);
+      MSC_HIPCK(hipGetLastError());
+      hipLaunchKernelGGL((k_fft3_x_solve<CT, TM>), dim3(F.NBy * ng), dim3(256), xb, st, F);
+      MSC_HIPCK(hipGetLastError());
+      hipLaunchKernelGGL((k_fft3_y_inv<CT, TM>), dim3(F.Nx * ng), dim3(256), yb, st, F);
+      MSC_HIPCK(hipGetLastError());
+      hipLaunchKernelGGL((k_fft3_z_inv<CT, TM>), dim3(gz), dim3(256), zb, st, F);
+      MSC_HIPCK(hipGetLastError());
+    }
   }
 };
 

@@ -308,3 +308,61 @@ def test_checkpoint_roundtrip(M, orc):
     m_b = s.moments()
     assert rel(m_b, m_a) <= 1e-13
     s.close()
+
+
+# ------------------------------------------------------------------ D3Q19 --
+CORR_SHAPES_3D = [(8, 8, 8), (8, 4, 16), (16, 16, 16), (4, 8, 16), (32, 16, 8)]
+
+
+@pytest.mark.parametrize("shape", CORR_SHAPES_3D)
+def test_corrected_iteration_3d_fp64(M, orc, shape):
+    say("correct3d", shape)
+    f, h = _rand_state(orc, 3, shape, seed=11 + sum(shape))
+    a = 3.0 / 128.0
+    s = _solver(M, shape)
+    fn, dm, R = s.correct(f, h, a)
+    ofn, _, _, odm, oR = orc.corrected_iteration(f, h, a, 1.0, 1.0, NU)
+    assert rel(dm, odm) <= 1e-12
+    assert rel(fn, ofn) <= 1e-12
+    assert abs(R - oR) <= 1e-12 * oR
+    s.close()
+
+
+def test_tgv3d_per_step_fp64(M, orc):
+    """3D Taylor-Green plus seeded perturbation, N = 16, dt = 16: one step at a
+    time from the oracle's state, replayed inner counts, all fields <= 1e-12."""
+    N = 16
+    p0, u0 = W.tgv3d_perturbed(N, NU / N, seed=1, jmax=4)
+    shape = (N, N, N)
+    state, bc = orc.initial_state(p0, u0), 0
+    s = _solver(M, shape, dt=16.0, eps=1e-10, p0=p0, u0=u0, n_min=1)
+    for n in range(5):
+        rc, nxt, nbc, st = orc.march_state(state, bc, shape, dt=16.0, nsteps=1, eps=1e-10, nmin=1)
+        assert rc == 0
+        K = st[0]["iters"]
+        s.set_state(state, bc)
+        s.set_schedule([K])
+        rc, gst = s.bdf2_step(1)
+        assert rc == 0 and gst[0]["iters"] == K
+        g, gbc = s.get_state()
+        assert gbc == nbc
+        for a, b in zip(_state_parts(g, 3, shape), _state_parts(nxt, 3, shape)):
+            assert rel(a, b) <= 1e-12, n
+        state, bc = nxt, nbc
+    s.close()
+
+
+def test_tgv3d_fp32_vs_fp64_oracle(M, orc):
+    N = 32
+    p0, u0 = W.tgv3d_perturbed(N, NU / N, seed=1, jmax=8)
+    ref = orc.march(p0, u0, dt=32.0, nsteps=3, eps=1e-10, nmin=1)
+    K = [st["iters"] for st in ref.stats]
+    s = _solver(M, (N, N, N), dt=32.0, eps=1e-10, storage="fp32", p0=p0, u0=u0, n_min=1)
+    s.set_schedule(K)
+    rc, _ = s.bdf2_step(3)
+    assert rc == 0
+    m = s.moments()
+    err = math.sqrt(((m[1:] - ref.m[1:]) ** 2).sum(0).mean()) / math.sqrt((ref.m[1:] ** 2).sum(0).mean())
+    say("fp32 3d rel velocity error", err)
+    assert err <= 1e-5
+    s.close()
