@@ -360,6 +360,120 @@ void reconstruct(const Lattice& L, const Grid& G, const double* f, const double*
   }
 }
 
+// ------------------------------------------------------------ adjoint --
+// Discrete adjoint (transpose) of the sweep with respect to f and h.  The
+// forward map at a site is M = P f, m = (M + h/2)/(1 + a/2), s = h - a m,
+// C = Eq. (collision) with feq(m) (Eq. feq) and Phi(m, s) (Eq.
+// source-distribution); push streaming fT_k(x + c_k) = C_k(x).  Given the
+// adjoint lamT of fT, accumulates lam_f += (dT/df)^T lamT and
+// lam_h += (dT/dh)^T lamT.  The streaming transpose is a pull:
+// mu_k(x) = lamT_k(x + c_k).
+void sweep_adjoint(const Lattice& L, const Grid& G, const double* f, const double* h, double a,
+                   double wp, double wm, const double* lamT, double* lam_f, double* lam_h) {
+  const int Q = L.Q, D = L.d;
+  const int64_t NS = G.NS;
+  for (int64_t x = 0; x < NS; ++x) {
+    int cx, cy, cz;
+    G.coords(x, cx, cy, cz);
+    double fs[19], mu[19], M[4], m[4], s[4], hh[4] = {0, 0, 0, 0};
+    for (int k = 0; k < Q; ++k) {
+      fs[k] = f[k * NS + x];
+      int xd = Grid::wrap(cx + L.c[k][0], G.n[0]);
+      int yd = Grid::wrap(cy + L.c[k][1], G.n[1]);
+      int zd = (D == 3) ? Grid::wrap(cz + L.c[k][2], G.n[2]) : 0;
+      mu[k] = lamT[k * NS + G.site(xd, yd, zd)];
+    }
+    if (h)
+      for (int b = 0; b <= D; ++b) hh[b] = h[b * NS + x];
+    moments(L, fs, M);
+    for (int b = 0; b <= D; ++b) {
+      m[b] = (M[b] + hh[b] / 2.0) / (1.0 + a / 2.0);
+      s[b] = hh[b] - a * m[b];
+    }
+    // even / odd parts of the incoming adjoint
+    double g[19], pp[19];
+    for (int k = 0; k < Q; ++k) {
+      int kb = L.opp[k];
+      double np = 0.5 * (mu[k] + mu[kb]), nm = 0.5 * (mu[k] - mu[kb]);
+      // direct dependence of C on f: (I - w+ Pi+ - w- Pi-)
+      lam_f[k * NS + x] += mu[k] - wp * np - wm * nm;
+      g[k] = wp * np + wm * nm;                             // adjoint entering feq
+      pp[k] = (1.0 - wp / 2.0) * np + (1.0 - wm / 2.0) * nm;  // adjoint entering Phi
+    }
+    // derivatives of Eq. (feq) and Eq. (source-distribution)
+    double lm[4] = {0, 0, 0, 0}, ls[4] = {0, 0, 0, 0};
+    for (int k = 0; k < Q; ++k) {
+      double cu = 0.0, cs = 0.0;
+      for (int al = 0; al < D; ++al) {
+        cu += L.c[k][al] * m[1 + al];
+        cs += L.c[k][al] * s[1 + al];
+      }
+      lm[0] += L.w[k] * g[k];  // d feq / d p
+      ls[0] += L.w[k] * pp[k];  // d Phi / d s0
+      for (int ga = 0; ga < D; ++ga) {
+        double ckg = L.c[k][ga];
+        // d feq_k / d u_g = w_k [ c_g/cs2 + (c.u) c_g/cs2^2 - u_g/cs2 ]
+        lm[1 + ga] += L.w[k] * (ckg / cs2 + cu * ckg / (cs2 * cs2) - m[1 + ga] / cs2) * g[k];
+        // d Phi_k / d u_g at fixed s = w_k [ -s_g/cs2 + c_g (c.s_u)/cs2^2 ]
+        lm[1 + ga] += L.w[k] * (-s[1 + ga] / cs2 + ckg * cs / (cs2 * cs2)) * pp[k];
+        // d Phi_k / d s_g = w_k [ (c_g - u_g)/cs2 + (c.u) c_g / cs2^2 ]
+        ls[1 + ga] += L.w[k] * ((ckg - m[1 + ga]) / cs2 + cu * ckg / (cs2 * cs2)) * pp[k];
+      }
+    }
+    // s = h - a m, m = (P f + h/2)/(1 + a/2)
+    double lmt[4];
+    for (int b = 0; b <= D; ++b) lmt[b] = lm[b] - a * ls[b];
+    if (lam_h)
+      for (int b = 0; b <= D; ++b) lam_h[b * NS + x] += ls[b] + lmt[b] * 0.5 / (1.0 + a / 2.0);
+    for (int k = 0; k < Q; ++k) {
+      double v = lmt[0];
+      for (int al = 0; al < D; ++al) v += L.c[k][al] * lmt[1 + al];
+      lam_f[k * NS + x] += v / (1.0 + a / 2.0);
+    }
+  }
+}
+
+// Transpose of the shadow operator dm = F^{-1}[chi H^{-1} F[.]] under the real
+// inner product: F^{-1}[chi H^{-H} F[.]] (the multiplier is replaced by its
+// conjugate transpose; the transform pair is self-adjoint up to the 1/N_Omega
+// that F^{-1} carries).  H^{-H} is applied by block elimination of
+// H^H = [[a, -i cs2 k^T], [-i k, b I]], b = a + nu |k|^2:
+//   y_p = (r_p + i cs2 k.r_u / b) / (a + cs2 |k|^2 / b),  y_u = (r_u + i k y_p)/b.
+void shadow_adjoint_field(const Grid& G, const double* y, double a, double nu, double* out) {
+  const int D = G.d;
+  const int64_t NS = G.NS;
+  std::vector<std::vector<cplx>> rh(D + 1, std::vector<cplx>(NS));
+  for (int b = 0; b <= D; ++b) {
+    for (int64_t s = 0; s < NS; ++s) rh[b][s] = cplx(y[b * NS + s], 0.0);
+    fft_nd(G, rh[b], -1);
+  }
+  std::vector<std::vector<cplx>> sol(D + 1, std::vector<cplx>(NS, cplx(0.0, 0.0)));
+  const cplx I(0.0, 1.0);
+  for (int64_t s = 0; s < NS; ++s) {
+    int c[3];
+    G.coords(s, c[0], c[1], c[2]);
+    bool keep = true;
+    double k[3] = {0, 0, 0}, kk = 0.0;
+    for (int ax = 0; ax < D; ++ax) {
+      int sj = signed_index(c[ax], G.n[ax]);
+      if (!in_mask(sj, G.n[ax])) keep = false;
+      k[ax] = 2.0 * kPi * sj / G.n[ax];
+      kk += k[ax] * k[ax];
+    }
+    if (!keep) continue;
+    double bcoef = a + nu * kk;
+    cplx kdotr(0.0, 0.0);
+    for (int ax = 0; ax < D; ++ax) kdotr += k[ax] * rh[1 + ax][s];
+    cplx yp = (rh[0][s] + I * cs2 * kdotr / bcoef) / (a + cs2 * kk / bcoef);
+    sol[0][s] = yp;
+    for (int ax = 0; ax < D; ++ax) sol[1 + ax][s] = (rh[1 + ax][s] + I * k[ax] * yp) / bcoef;
+  }
+  for (int b = 0; b <= D; ++b) {
+    fft_nd(G, sol[b], +1);
+    for (int64_t s = 0; s < NS; ++s) out[b * NS + s] = sol[b][s].real();
+  }
+}
+
 bool is_fin(double v) { return std::isfinite(v); }
 
 }  // namespace
@@ -676,6 +790,197 @@ int orc_march(const orc_params* P, const double* p0, const double* u0, int nstep
   if (f_out) std::memcpy(f_out, state.data(), sizeof(double) * FQ);
   if (m_out) std::memcpy(m_out, state.data() + 3 * FQ, sizeof(double) * FM);
   return rc;
+}
+
+// Adjoint of one sweep (see sweep_adjoint): lam_f and lam_h are
+// accumulated (+=); h and lam_h may be NULL.
+int orc_sweep_adjoint(int d, const int* n, const double* f, const double* h, double a, double wp,
+                      double wm, const double* lamT, double* lam_f, double* lam_h) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  sweep_adjoint(L, G, f, h, a, wp, wm, lamT, lam_f, lam_h);
+  return ORC_OK;
+}
+
+int orc_shadow_adjoint(int d, const int* n, const double* y, double a, double nu, double* out) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Grid G(d, n);
+  shadow_adjoint_field(G, y, a, nu, out);
+  return ORC_OK;
+}
+
+// Discrete adjoint of orc_march_state over nsteps steps replayed at the inner
+// counts `schedule` (required).  lam: adjoint of the final state (same layout
+// as the state), overwritten with the adjoint of the initial state.  The
+// forward is recomputed from state0 (step checkpoints, then the inner iterates
+// of each step in reverse order).
+int orc_march_adjoint(const orc_params* P, const double* state0, int64_t bdf_count0, int nsteps,
+                      const int* schedule, double* lam) {
+  const int d = P->d;
+  if ((d != 2 && d != 3) || !schedule) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, P->n);
+  const int Q = L.Q, D = d;
+  const int64_t NS = G.NS;
+  const size_t FQ = (size_t)Q * NS, FM = (size_t)(D + 1) * NS, SZ = 3 * FQ + 2 * FM;
+  const double wp = 1.0 / P->tau_plus, wm = 1.0 / P->tau_minus;
+  const double nu = cs2 * (P->tau_plus - 0.5);
+  // forward checkpoints of the state at the start of every step
+  std::vector<std::vector<double>> ck(nsteps + 1, std::vector<double>(SZ));
+  std::memcpy(ck[0].data(), state0, sizeof(double) * SZ);
+  int64_t bc = bdf_count0;
+  for (int n = 0; n < nsteps; ++n) {
+    ck[n + 1] = ck[n];
+    int done = 0;
+    int rc = orc_march_state(P, ck[n + 1].data(), &bc, 1, schedule + n, nullptr, nullptr, &done);
+    if (rc != ORC_OK) return rc;
+  }
+  std::vector<double> lf0(FQ), lf1(FQ), lf2(FQ), lm0(FM), lm1(FM);
+  std::memcpy(lf0.data(), lam, sizeof(double) * FQ);
+  std::memcpy(lf1.data(), lam + FQ, sizeof(double) * FQ);
+  std::memcpy(lf2.data(), lam + 2 * FQ, sizeof(double) * FQ);
+  std::memcpy(lm0.data(), lam + 3 * FQ, sizeof(double) * FM);
+  std::memcpy(lm1.data(), lam + 3 * FQ + FM, sizeof(double) * FM);
+  std::vector<double> h(FM), lh(FM), Pr(FM), dm(FM), y(FM), z(FM);
+  std::vector<double> LT(FQ), LF(FQ), carry(FQ);
+  for (int n = nsteps - 1; n >= 0; --n) {
+    const double* S = ck[n].data();
+    const double *fn = S, *fn1 = S + FQ, *fn2 = S + 2 * FQ, *mn = S + 3 * FQ, *mn1 = S + 3 * FQ + FM;
+    const int64_t bcn = bdf_count0 + n;
+    const int q = (bcn == 0) ? 1 : 2;
+    const double a = (q == 1) ? 1.0 / P->dt : 3.0 / (2.0 * P->dt);
+    const int64_t cap = (P->extrap_states == 0) ? 2 : P->extrap_states - 1;
+    const int64_t order = std::min<int64_t>(bcn, cap);
+    const int K = schedule[n];
+    // recompute h, the trial and the inner iterates f^(1..K)
+    for (size_t i = 0; i < FM; ++i) h[i] = (q == 1) ? mn[i] / P->dt : (4.0 * mn[i] - mn1[i]) / (2.0 * P->dt);
+    std::vector<std::vector<double>> fl(K + 1, std::vector<double>(FQ));
+    for (size_t i = 0; i < FQ; ++i) {
+      if (order == 0)
+        fl[1][i] = fn[i];
+      else if (order == 1)
+        fl[1][i] = 2.0 * fn[i] - fn1[i];
+      else
+        fl[1][i] = 3.0 * fn[i] - 3.0 * fn1[i] + fn2[i];
+    }
+    std::vector<double> fT(FQ);
+    for (int ell = 1; ell < K; ++ell) {
+      double R;
+      sweep(L, G, fl[ell].data(), h.data(), a, wp, wm, fT.data(), Pr.data(), &R);
+      if (P->corrector == 1) {
+        shadow_field(G, Pr.data(), a, nu, dm.data());
+        lift_add(L, G, fT.data(), dm.data(), fl[ell + 1].data());
+      } else {
+        fl[ell + 1] = fT;
+      }
+    }
+    // new state: f^n' = fT^(K), f^{n-1}' = f^n, f^{n-2}' = f^{n-1},
+    // m^n' = (P fT^(K) + h/2)/(1 + a/2), m^{n-1}' = m^n
+    std::fill(lh.begin(), lh.end(), 0.0);
+    for (int64_t x = 0; x < NS; ++x)
+      for (int k = 0; k < Q; ++k) {
+        double v = lm0[x];
+        for (int al = 0; al < D; ++al) v += L.c[k][al] * lm0[(1 + al) * NS + x];
+        LT[k * NS + x] = lf0[k * NS + x] + v / (1.0 + a / 2.0);
+      }
+    for (size_t i = 0; i < FM; ++i) lh[i] = lm0[i] * 0.5 / (1.0 + a / 2.0);
+    std::vector<double> nlf0(lf1), nlf1(lf2), nlf2(FQ, 0.0), nlm0(lm1), nlm1(FM, 0.0);
+    std::fill(carry.begin(), carry.end(), 0.0);
+    for (int ell = K; ell >= 1; --ell) {
+      // Lambda_ell = carry + (dT/df at f^(ell))^T LT
+      LF = carry;
+      sweep_adjoint(L, G, fl[ell].data(), h.data(), a, wp, wm, LT.data(), LF.data(), lh.data());
+      if (ell == 1) break;
+      if (P->corrector == 1) {
+        // f^(ell) = fT^(ell-1) + E Sh P (fT^(ell-1) - f^(ell-1))
+        for (int64_t x = 0; x < NS; ++x) {
+          double acc[4] = {0, 0, 0, 0};
+          for (int k = 0; k < Q; ++k) {
+            acc[0] += L.w[k] * LF[k * NS + x];
+            for (int al = 0; al < D; ++al) acc[1 + al] += L.w[k] * L.c[k][al] / cs2 * LF[k * NS + x];
+          }
+          for (int b = 0; b <= D; ++b) y[b * NS + x] = acc[b];
+        }
+        shadow_adjoint_field(G, y.data(), a, nu, z.data());
+        for (int64_t x = 0; x < NS; ++x)
+          for (int k = 0; k < Q; ++k) {
+            double v = z[x];
+            for (int al = 0; al < D; ++al) v += L.c[k][al] * z[(1 + al) * NS + x];
+            LT[k * NS + x] = LF[k * NS + x] + v;
+            carry[k * NS + x] = -v;
+          }
+      } else {
+        LT = LF;
+        std::fill(carry.begin(), carry.end(), 0.0);
+      }
+    }
+    // trial extrapolation and h_q
+    for (size_t i = 0; i < FQ; ++i) {
+      if (order == 0) {
+        nlf0[i] += LF[i];
+      } else if (order == 1) {
+        nlf0[i] += 2.0 * LF[i];
+        nlf1[i] -= LF[i];
+      } else {
+        nlf0[i] += 3.0 * LF[i];
+        nlf1[i] -= 3.0 * LF[i];
+        nlf2[i] += LF[i];
+      }
+    }
+    for (size_t i = 0; i < FM; ++i) {
+      if (q == 1) {
+        nlm0[i] += lh[i] / P->dt;
+      } else {
+        nlm0[i] += 4.0 * lh[i] / (2.0 * P->dt);
+        nlm1[i] -= lh[i] / (2.0 * P->dt);
+      }
+    }
+    lf0.swap(nlf0);
+    lf1.swap(nlf1);
+    lf2.swap(nlf2);
+    lm0.swap(nlm0);
+    lm1.swap(nlm1);
+  }
+  std::memcpy(lam, lf0.data(), sizeof(double) * FQ);
+  std::memcpy(lam + FQ, lf1.data(), sizeof(double) * FQ);
+  std::memcpy(lam + 2 * FQ, lf2.data(), sizeof(double) * FQ);
+  std::memcpy(lam + 3 * FQ, lm0.data(), sizeof(double) * FM);
+  std::memcpy(lam + 3 * FQ + FM, lm1.data(), sizeof(double) * FM);
+  return ORC_OK;
+}
+
+// Adjoint of the initial state map (orc_initial_state): the state is
+// (f0, f0, f0, P f0, P f0) with f0 = feq(p0, u0).  Writes lam_p0 (NS) and
+// lam_u0 (d NS).
+int orc_initial_state_adjoint(int d, const int* n, const double* p0, const double* u0,
+                              const double* lam, double* lam_p0, double* lam_u0) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  const int Q = L.Q, D = d;
+  const int64_t NS = G.NS;
+  const size_t FQ = (size_t)Q * NS, FM = (size_t)(D + 1) * NS;
+  for (int64_t x = 0; x < NS; ++x) {
+    double m[4] = {p0[x], 0, 0, 0};
+    for (int al = 0; al < D; ++al) m[1 + al] = u0[al * NS + x];
+    double lp = 0.0, lu[3] = {0, 0, 0};
+    for (int k = 0; k < Q; ++k) {
+      double lk = lam[k * NS + x] + lam[FQ + k * NS + x] + lam[2 * FQ + k * NS + x];
+      for (int b = 0; b <= D; ++b) {
+        double pb = (b == 0) ? 1.0 : L.c[k][b - 1];
+        lk += pb * (lam[3 * FQ + b * NS + x] + lam[3 * FQ + FM + b * NS + x]);
+      }
+      double cu = 0.0;
+      for (int al = 0; al < D; ++al) cu += L.c[k][al] * m[1 + al];
+      lp += L.w[k] * lk;
+      for (int ga = 0; ga < D; ++ga)
+        lu[ga] += L.w[k] * (L.c[k][ga] / cs2 + cu * L.c[k][ga] / (cs2 * cs2) - m[1 + ga] / cs2) * lk;
+    }
+    lam_p0[x] = lp;
+    for (int ga = 0; ga < D; ++ga) lam_u0[ga * NS + x] = lu[ga];
+  }
+  return ORC_OK;
 }
 
 }  // extern "C"

@@ -90,7 +90,13 @@ def lib():
         L.orc_march_state.argtypes = [ctypes.POINTER(OrcParams), _dp, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.c_int, _ip, ctypes.POINTER(OrcStepStats), _dp, _ip]
         L.orc_initial_state.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp]
-        for name in ("orc_march_state", "orc_initial_state", "orc_lattice", "orc_sweep", "orc_shadow", "orc_corrected_iteration", "orc_fft",
+        L.orc_sweep_adjoint.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _dp, _dp, _dp]
+        L.orc_shadow_adjoint.argtypes = [ctypes.c_int, _ip, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_march_adjoint.argtypes = [ctypes.POINTER(OrcParams), _dp, ctypes.c_int64, ctypes.c_int, _ip, _dp]
+        L.orc_initial_state_adjoint.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp, _dp, _dp]
+        for name in ("orc_sweep_adjoint", "orc_shadow_adjoint", "orc_march_adjoint", "orc_initial_state_adjoint",
+                     "orc_march_state", "orc_initial_state", "orc_lattice", "orc_sweep", "orc_shadow", "orc_corrected_iteration", "orc_fft",
                      "orc_tables", "orc_init_populations", "orc_moments", "orc_explicit",
                      "orc_march"):
             getattr(L, name).restype = ctypes.c_int
@@ -322,3 +328,50 @@ def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_p
                   converged=s.converged) for s in st[: nsteps]]
     return MarchResult(rc, done.value, f, m, stats,
                        Rh.reshape(nsteps, kmax) if Rh is not None else None)
+
+
+# ------------------------------------------------------------------ adjoint --
+def sweep_adjoint(f, h, a, wp, wm, lamT):
+    """(lam_f, lam_h) = transposes of dT/df and dT/dh applied to lamT."""
+    f, lamT = _c64(f), _c64(lamT)
+    d = f.ndim - 1
+    lf = np.zeros_like(f)
+    lh = np.zeros((d + 1,) + f.shape[1:])
+    hh = _c64(h) if h is not None else None
+    rc = lib().orc_sweep_adjoint(d, _dims(f.shape[1:]), _p(f), _p(hh) if hh is not None else None, a, wp, wm,
+                                 _p(lamT), _p(lf), _p(lh))
+    assert rc == 0
+    return lf, lh
+
+
+def shadow_adjoint(y, a, nu):
+    y = _c64(y)
+    d = y.ndim - 1
+    out = np.zeros_like(y)
+    rc = lib().orc_shadow_adjoint(d, _dims(y.shape[1:]), _p(y), a, nu, _p(out))
+    assert rc == 0
+    return out
+
+
+def march_adjoint(state0, bdf_count0, shape, lam_final, *, dt, schedule, eps=1e-10, kmax=300, nmin=2,
+                  corrector=1, tau_plus=1.0, tau_minus=1.0, extrap_states=0):
+    """Adjoint of the state map of march_state at the given inner counts."""
+    d = len(shape)
+    P = _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extrap_states)
+    lam = np.array(lam_final, dtype=np.float64, copy=True)
+    sched = np.ascontiguousarray(schedule, dtype=np.int32)
+    st = _c64(state0)
+    rc = lib().orc_march_adjoint(ctypes.byref(P), _p(st), int(bdf_count0), len(sched),
+                                 sched.ctypes.data_as(_ip), _p(lam))
+    assert rc == 0, rc
+    return lam
+
+
+def initial_state_adjoint(p0, u0, lam_state):
+    p0, u0, lam = _c64(p0), _c64(u0), _c64(lam_state)
+    d = u0.shape[0]
+    lp = np.zeros_like(p0)
+    lu = np.zeros_like(u0)
+    rc = lib().orc_initial_state_adjoint(d, _dims(p0.shape), _p(p0), _p(u0), _p(lam), _p(lp), _p(lu))
+    assert rc == 0
+    return lp, lu
