@@ -118,9 +118,10 @@ msc_status msc_params_default(msc_params* p, int32_t lattice, int32_t n, double 
  * Errors: MSC_ERR_INVALID_ARG (extent not a power of two or < 4, tau <= 1/2,
  * dt <= 0, eps <= 0, k_max < 1, n_min < 1, unknown lattice/storage/corrector,
  * NULL pointers); MSC_ERR_OUT_OF_MEMORY; MSC_ERR_DEVICE; MSC_ERR_UNSUPPORTED
- * for a grid larger than the transform kernels support (2D: 4096 per side in
- * FP32, 2048 in FP64; 3D: 512).  *out is owned by the library until
- * msc_free. */
+ * with the shadow corrector for a grid larger than the transform kernels
+ * support (2D: x extent up to 2048 in FP32 and 1024 in FP64, y extent up to
+ * 4096 and 2048; 3D: every extent up to 2048 and 1024).  *out is owned by
+ * the library until msc_free. */
 msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, msc_ctx** out);
 
 /* Advance nsteps physical steps by Algorithm 1 (or Picard with
@@ -199,6 +200,45 @@ msc_status msc_set_schedule(msc_ctx* c, const int32_t* K, int32_t nsteps);
 msc_status msc_state_size(const msc_ctx* c, int64_t* n_doubles);
 msc_status msc_get_state(msc_ctx* c, double* state, int64_t* bdf_count);
 msc_status msc_set_state(msc_ctx* c, const double* state, int64_t bdf_count);
+
+/* Discrete adjoint of the march (the transpose of the unrolled computation:
+ * inner iterations of Alg. 1 at their accepted counts, Eq. sweep, schur,
+ * shadow-update, lift, macro-reconstruct, bdf2 and the trial
+ * extrapolation).  It is an extension of the method, which defines no
+ * adjoint; it differentiates the discrete map, acceptance counts held fixed.
+ *
+ * msc_set_recording(c, 1) clears earlier records and makes every later
+ * msc_bdf2_step keep, per accepted step, a device checkpoint of the state at
+ * the step's start (the five arrays of msc_get_state in the storage
+ * precision, m in FP64), its BDF count and its inner count K_n.  While
+ * recording, msc_bdf2_step synchronises once per physical step.  A step that
+ * fails is not recorded.  msc_set_recording(c, 0) stops and frees the
+ * records; a new context does not record.  msc_recorded_steps returns their
+ * number. */
+msc_status msc_set_recording(msc_ctx* c, int32_t enable);
+msc_status msc_recorded_steps(const msc_ctx* c, int32_t* count);
+
+/* Backward pass over the last nsteps recorded steps (1 <= nsteps <= the
+ * recorded count), which are consumed, so successive calls walk further back.
+ * lam holds msc_state_size FP64 values in the msc_get_state layout: on entry
+ * the adjoint (gradient) of a scalar loss with respect to the state after
+ * the last of those steps, on return its adjoint with respect to the state
+ * before the first of them.  Each step's inner iterates are recomputed in
+ * FP64 from its checkpoint, and all adjoint arithmetic (transforms included)
+ * is FP64, whatever the storage precision.  lam is a device pointer when
+ * on_device is nonzero.  MSC_ERR_INVALID_ARG for nsteps outside that range;
+ * MSC_ERR_UNSUPPORTED with the shadow corrector where the FP64 transforms do
+ * not fit (2D: x extent > 1024 or y extent > 2048; 3D: an extent > 1024).
+ * The march state is not changed. */
+msc_status msc_bdf2_adjoint(msc_ctx* c, int32_t nsteps, double* lam, int32_t on_device);
+
+/* Adjoint of msc_init's map from (p_hat0, u0) to the initial state
+ * (f0, f0, f0, P f0, P f0) with f0 = feq(p_hat0, u0) (Eq. feq, moments):
+ * given lam (msc_state_size values), writes lam_phat0 (N_sites) and lam_u0
+ * (d*N_sites).  All five arrays are host FP64 unless on_device is nonzero.
+ * Does not change the march state. */
+msc_status msc_init_adjoint(msc_ctx* c, const double* phat0, const double* u0, const double* lam,
+                            double* lam_phat0, double* lam_u0, int32_t on_device);
 
 /* Kernel timing for roofline reports: when enabled, every launch of the
  * population sweep kernel is bracketed by HIP events on the context's stream

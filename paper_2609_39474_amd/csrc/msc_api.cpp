@@ -218,6 +218,31 @@ msc_status msc_set_state(msc_ctx* c, const double* state, int64_t bdf_count) {
   return fwd(c, c->s->set_state(state, bdf_count));
 }
 
+msc_status msc_set_recording(msc_ctx* c, int32_t enable) {
+  if (!c) return MSC_ERR_INVALID_ARG;
+  if (c->s->broken) return MSC_ERR_STATE;
+  return fwd(c, c->s->set_recording(enable));
+}
+
+msc_status msc_recorded_steps(const msc_ctx* c, int32_t* count) {
+  if (!c || !count) return MSC_ERR_INVALID_ARG;
+  *count = c->s->recorded_steps();
+  return MSC_OK;
+}
+
+msc_status msc_bdf2_adjoint(msc_ctx* c, int32_t nsteps, double* lam, int32_t on_device) {
+  if (!c || !lam) return MSC_ERR_INVALID_ARG;
+  if (c->s->broken) return MSC_ERR_STATE;
+  return fwd(c, c->s->bdf2_adjoint(nsteps, lam, on_device != 0));
+}
+
+msc_status msc_init_adjoint(msc_ctx* c, const double* phat0, const double* u0, const double* lam,
+                            double* lam_phat0, double* lam_u0, int32_t on_device) {
+  if (!c || !phat0 || !u0 || !lam || !lam_phat0 || !lam_u0) return MSC_ERR_INVALID_ARG;
+  if (c->s->broken) return MSC_ERR_STATE;
+  return fwd(c, c->s->init_adjoint(phat0, u0, lam, lam_phat0, lam_u0, on_device != 0));
+}
+
 msc_status msc_set_kernel_timing(msc_ctx* c, int32_t enable) {
   if (!c) return MSC_ERR_INVALID_ARG;
   if (c->s->broken) return MSC_ERR_STATE;

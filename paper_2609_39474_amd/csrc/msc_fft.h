@@ -139,6 +139,32 @@ __device__ __forceinline__ void schur_solve(const double* kv, const double (*r)[
   }
 }
 
+// Eq. (schur) conjugate-transposed, for the adjoint of the correction:
+// solve H^H y = r, H^H = [[a, -i cs2 k^T], [-i k, b I]], b = a + nu |k|^2:
+//   y_p = (r_p + i cs2 (k.r_u)/b) / (a + cs2 |k|^2 / b),  y_u = (r_u + i k y_p)/b.
+template <int D>
+__device__ __forceinline__ void schur_solve_adjoint(const double* kv, const double (*r)[2], double a, double nu,
+                                                    double scale, double (*out)[2]) {
+  const double cs2 = 1.0 / 3.0;
+  double kk = 0.0;
+  for (int b = 0; b < D; ++b) kk += kv[b] * kv[b];
+  const double bc = a + nu * kk;
+  double kr_re = 0.0, kr_im = 0.0;
+  for (int b = 0; b < D; ++b) {
+    kr_re += kv[b] * r[1 + b][0];
+    kr_im += kv[b] * r[1 + b][1];
+  }
+  const double den = a + cs2 * kk / bc;
+  const double yp_re = (r[0][0] - cs2 * kr_im / bc) / den;
+  const double yp_im = (r[0][1] + cs2 * kr_re / bc) / den;
+  out[0][0] = yp_re * scale;
+  out[0][1] = yp_im * scale;
+  for (int b = 0; b < D; ++b) {
+    out[1 + b][0] = (r[1 + b][0] - kv[b] * yp_im) / bc * scale;
+    out[1 + b][1] = (r[1 + b][1] + kv[b] * yp_re) / bc * scale;
+  }
+}
+
 // Guard shared by the correction kernels: run only right after sweep ell of
 // step n without acceptance (Algorithm 1 mode), or always (diagnostic mode).
 struct CorrGuard {
@@ -155,6 +181,7 @@ template <class CT, class TM>
 struct Fft2Args {
   CorrGuard g;
   int do_accept;  // first pass also reconstructs m^{n+1} when step n accepted at ell
+  int adjoint;    // apply chi H^{-H} (transpose of the correction) instead of chi H^{-1}
   int Nx, Ny, lgx, lgy;
   int NBy;      // N_y/4 + 1
   int rows_per_block, cols_per_block;
@@ -241,7 +268,10 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Fft2Args<CT, TM> A) {
         r[f][0] = (double)v.x;
         r[f][1] = (double)v.y;
       }
-      schur_solve<2>(kv, r, A.a, A.nu, A.inv_ns, o);
+      if (A.adjoint)
+        schur_solve_adjoint<2>(kv, r, A.a, A.nu, A.inv_ns, o);
+      else
+        schur_solve<2>(kv, r, A.a, A.nu, A.inv_ns, o);
       for (int f = 0; f < 3; ++f) G[(f * JB + c) * Nx + jx] = {(CT)o[f][0], (CT)o[f][1]};
     } else {
       for (int f = 0; f < 3; ++f) G[(f * JB + c) * Nx + jx] = {(CT)0, (CT)0};
@@ -321,6 +351,7 @@ template <class CT, class TM>
 struct Fft3Args {
   CorrGuard g;
   int do_accept;
+  int adjoint;
   int Nx, Ny, Nz, lgx, lgy, lgz;
   int NBz;  // N_z/4 + 1
   int NBy;  // 2 (N_y/4) + 1 retained y indices
@@ -437,7 +468,10 @@ __global__ __launch_bounds__(256) void k_fft3_x_solve(Fft3Args<CT, TM> A) {
         r[f][0] = (double)v.x;
         r[f][1] = (double)v.y;
       }
-      schur_solve<3>(kv, r, A.a, A.nu, A.inv_ns, o);
+      if (A.adjoint)
+        schur_solve_adjoint<3>(kv, r, A.a, A.nu, A.inv_ns, o);
+      else
+        schur_solve<3>(kv, r, A.a, A.nu, A.inv_ns, o);
       for (int f = 0; f < 4; ++f) Gb[(f * JB + c) * Nx + jx] = {(CT)o[f][0], (CT)o[f][1]};
     } else {
       for (int f = 0; f < 4; ++f) Gb[(f * JB + c) * Nx + jx] = {(CT)0, (CT)0};

@@ -52,6 +52,11 @@ class SolverBase {
   virtual msc_status set_state(const double* state, int64_t bdf_count) = 0;
   virtual msc_status set_kernel_timing(int enable) = 0;
   virtual msc_status kernel_time(int kind, double* seconds, int64_t* launches, double* bytes) = 0;
+  virtual msc_status set_recording(int enable) = 0;
+  virtual int32_t recorded_steps() const = 0;
+  virtual msc_status bdf2_adjoint(int32_t nsteps, double* lam, bool on_device) = 0;
+  virtual msc_status init_adjoint(const double* phat0, const double* u0, const double* lam, double* lam_phat0,
+                                  double* lam_u0, bool on_device) = 0;
   virtual Tuning& tuning() = 0;
   virtual msc_status reconfigure() = 0;  // re-pick launch shapes after a tuning change
 

@@ -6,9 +6,10 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
-#include "msc_fft.h"
+#include "msc_adjoint.h"
 #include "msc_solver.h"
 
 namespace msc {
@@ -89,6 +90,16 @@ void launch_sweep_d3(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hi
     default: launch_sweep_tile<D3Q19, T, TM, 256, 8, 32>(mode, A, grid, st); break;
   }
 }
+
+// Buffers of one run of the correction transforms in one precision.
+template <class CX, class TX>
+struct XformBufs {
+  const TX* in;
+  TX* out;
+  cpx<CX>* spec1;
+  cpx<CX>* spec2;
+  const cpx<CX>* tw[3];
+};
 
 // ----------------------------------------------------------------- solver --
 template <class L, class T>
@@ -181,8 +192,12 @@ class Solver : public SolverBase {
       int64_t bdf_dev = bdf_count;
       int batch = 1;
       msc_status rc = MSC_OK;
+      if (recording) pull_ctl();
       while (n_dev < n_end) {
-        const int B = std::min(batch, n_end - n_dev);
+        // while recording, one step per synchronisation so that the state at
+        // each step's start can be checkpointed
+        const int B = recording ? 1 : std::min(batch, n_end - n_dev);
+        if (recording && ell_dev == 1) take_checkpoint(bdf_dev);
         for (int i = 0; i < B; ++i) {
           const int n = n_dev + i;
           const int64_t bc = bdf_dev + i;
@@ -207,6 +222,7 @@ class Solver : public SolverBase {
         const int pn = phase_n(ph), pell = phase_ell(ph);
         const uint32_t ps = phase_state(ph);
         if (ps == PH_FAILED) {
+          if (recording && !records.empty() && records.back().K == 0) drop_last_record();
           bdf_dev += (pn - n_dev);
           rc = (ctl_h->fail_code == 5) ? MSC_ERR_NONCONVERGED : MSC_ERR_NONFINITE;
           last_error = std::string(rc == MSC_ERR_NONCONVERGED ? "nonconvergent" : "non-finite residual") +
@@ -223,6 +239,7 @@ class Solver : public SolverBase {
           return rc;
         }
         if (ps == PH_ACCEPTED) {
+          if (recording && !records.empty() && records.back().K == 0) records.back().K = pell;
           bdf_dev += (pn - n_dev + 1);
           n_dev = pn + 1;
           ell_dev = 1;
@@ -430,6 +447,81 @@ class Solver : public SolverBase {
     });
   }
 
+  // ------------------------------------------------------------- adjoint --
+  msc_status set_recording(int enable) override {
+    return guard([&]() {
+      sync();
+      clear_records();
+      recording = enable != 0;
+      if (!recording) free_adjoint_buffers();
+      return MSC_OK;
+    });
+  }
+
+  int32_t recorded_steps() const override { return (int32_t)records.size(); }
+
+  msc_status bdf2_adjoint(int32_t nsteps, double* lam, bool on_device) override {
+    return guard([&]() -> msc_status {
+      if (nsteps < 1 || nsteps > (int32_t)records.size()) {
+        last_error = "nsteps must be between 1 and the number of recorded steps (" +
+                     std::to_string(records.size()) + ")";
+        return MSC_ERR_INVALID_ARG;
+      }
+      if (P.corrector == MSC_CORRECTOR_SHADOW && !fft_fits(sizeof(cpx<double>))) {
+        last_error = "the FP64 transforms of the adjoint correction do not fit this grid size";
+        return MSC_ERR_UNSUPPORTED;
+      }
+      int kmax = 1;
+      for (int r = 0; r < nsteps; ++r) kmax = std::max(kmax, records[records.size() - 1 - r].K);
+      ensure_adjoint_buffers(kmax);
+      const int64_t SZ = state_size();
+      double* cur = adj_lam[0];
+      double* nxt = adj_lam[1];
+      MSC_HIPCK(hipMemcpyAsync(cur, lam, sizeof(double) * SZ,
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+      for (int r = 0; r < nsteps; ++r) {
+        backward_step(records[records.size() - 1 - r], cur, nxt);
+        std::swap(cur, nxt);
+      }
+      MSC_HIPCK(hipMemcpyAsync(lam, cur, sizeof(double) * SZ,
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+      sync();
+      for (int r = 0; r < nsteps; ++r) drop_last_record();
+      return MSC_OK;
+    });
+  }
+
+  msc_status init_adjoint(const double* phat0, const double* u0, const double* lam, double* lam_phat0,
+                          double* lam_u0, bool on_device) override {
+    return guard([&]() -> msc_status {
+      const int64_t NS = G.NS, SZ = state_size();
+      const double *pd = phat0, *ud = u0, *ld = lam;
+      double *lp = lam_phat0, *lu = lam_u0;
+      double* tmp = nullptr;
+      if (!on_device) {
+        tmp = (double*)dalloc(sizeof(double) * (SZ + 2 * (D + 1) * NS));
+        double* t = tmp;
+        MSC_HIPCK(hipMemcpyAsync(t, phat0, sizeof(double) * NS, hipMemcpyHostToDevice, st));
+        MSC_HIPCK(hipMemcpyAsync(t + NS, u0, sizeof(double) * D * NS, hipMemcpyHostToDevice, st));
+        MSC_HIPCK(hipMemcpyAsync(t + (D + 1) * NS, lam, sizeof(double) * SZ, hipMemcpyHostToDevice, st));
+        pd = t;
+        ud = t + NS;
+        ld = t + (D + 1) * NS;
+        lp = t + (D + 1) * NS + SZ;
+        lu = lp + NS;
+      }
+      hipLaunchKernelGGL((k_adj_init<L>), dim3(ew_grid()), dim3(256), 0, st, NS, pd, ud, ld, lp, lu);
+      MSC_HIPCK(hipGetLastError());
+      if (!on_device) {
+        MSC_HIPCK(hipMemcpyAsync(lam_phat0, lp, sizeof(double) * NS, hipMemcpyDeviceToHost, st));
+        MSC_HIPCK(hipMemcpyAsync(lam_u0, lu, sizeof(double) * D * NS, hipMemcpyDeviceToHost, st));
+      }
+      sync();
+      if (tmp) dfree(tmp);
+      return MSC_OK;
+    });
+  }
+
   msc_status set_kernel_timing(int enable) override {
     return guard([&]() {
       sync();
@@ -515,6 +607,30 @@ class Solver : public SolverBase {
   double t_sum[2] = {0, 0};
   int64_t t_count[2] = {0, 0};
 
+  // adjoint records and buffers
+  struct Record {
+    void* mem;   // f^n, f^{n-1}, f^{n-2} (T), then m^n, m^{n-1} (FP64)
+    int64_t bc;  // BDF steps accepted before this step
+    int K;       // inner sweeps at acceptance; 0 while the step is in flight
+  };
+  bool recording = false;
+  std::vector<Record> records;
+  std::vector<void*> adj_allocs;
+  double* adj_lam[2] = {nullptr, nullptr};  // state-layout adjoints (in, out)
+  double* adj_LT = nullptr;
+  double* adj_LF = nullptr;
+  double* adj_carry = nullptr;
+  double* adj_lh = nullptr;
+  double* adj_h = nullptr;
+  double* adj_fT = nullptr;
+  double* adj_it = nullptr;  // FP64 inner iterates f^(1..K) of the step being reversed
+  int adj_it_cap = 0;
+  // FP64 transform buffers: P r of a recomputed sweep, or y = E^T Lambda, in
+  // adj_y; dm, or z = Sh^T y, out in adj_z
+  double* adj_y = nullptr;
+  double* adj_z = nullptr;
+  XformBufs<double, double> adj_x{};
+
   // ------------------------------------------------------------- helpers --
   template <class F>
   msc_status guard(F&& fn) {
@@ -568,8 +684,7 @@ class Solver : public SolverBase {
   bool corrector_supported() const { return fft_fits(); }
 
   // LDS of the transform passes at their minimum block shape
-  bool fft_fits() const {
-    const size_t c = sizeof(cpx<CT>);
+  bool fft_fits(size_t c = sizeof(cpx<CT>)) const {
     if (D == 2) return (size_t)4 * G.N2 * c <= 131072 && (size_t)6 * G.N0 * c <= 131072;
     const int Nmax = std::max(G.n[0], std::max(G.n[1], G.n[2]));
     return (size_t)4 * G.n[2] * c <= 131072 && (size_t)8 * Nmax * c <= 131072;
@@ -619,6 +734,10 @@ class Solver : public SolverBase {
     ev_live.clear();
     ev_free.clear();
     if (st) (void)hipStreamSynchronize(st);
+    for (auto& r : records) dfree(r.mem);
+    records.clear();
+    for (void* p : adj_allocs) dfree(p);
+    adj_allocs.clear();
     for (void* p : allocs) dfree(p);
     allocs.clear();
     if (ctl_h) (void)hipHostFree(ctl_h);
@@ -631,15 +750,17 @@ class Solver : public SolverBase {
     partials_h = nullptr;
   }
 
-  cpx<CT>* make_twiddles(int N) {
-    std::vector<cpx<CT>> t(N);
+  template <class CX = CT>
+  cpx<CX>* make_twiddles(int N, std::vector<void*>* owner = nullptr) {
+    std::vector<cpx<CX>> t(N);
     const double two_pi = 6.283185307179586476925286766559;
     for (int i = 0; i < N; ++i) {
       const double ang = -two_pi * (double)i / (double)N;
-      t[i] = {(CT)std::cos(ang), (CT)std::sin(ang)};
+      t[i] = {(CX)std::cos(ang), (CX)std::sin(ang)};
     }
-    cpx<CT>* d = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * N));
-    MSC_HIPCK(hipMemcpyAsync(d, t.data(), sizeof(cpx<CT>) * N, hipMemcpyHostToDevice, st));
+    cpx<CX>* d = (cpx<CX>*)dalloc(sizeof(cpx<CX>) * N);
+    (owner ? owner : &allocs)->push_back((void*)d);
+    MSC_HIPCK(hipMemcpyAsync(d, t.data(), sizeof(cpx<CX>) * N, hipMemcpyHostToDevice, st));
     sync();  // t goes out of scope
     return d;
   }
@@ -692,8 +813,12 @@ class Solver : public SolverBase {
     sync();
   }
 
-  // m^n = P f^n, m^{n-1} = m^n, BDF history reset (next step BDF1).
+  // m^n = P f^n, m^{n-1} = m^n, f^{n-1} = f^{n-2} = f^n, BDF history reset
+  // (next step BDF1, whose trial uses f^n alone).
   void reset_history_from_current() {
+    for (int i = 1; i < 3; ++i)
+      MSC_HIPCK(hipMemcpyAsync(fb.p[ctl_h->slot_hist[i]], fb.p[ctl_h->slot_hist[0]], sizeof(T) * Q * G.NS,
+                               hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL((k_moments<L, T>), dim3(ew_grid()), dim3(256), 0, st, fb.p[ctl_h->slot_hist[0]],
                        mb[ctl_h->slot_m[0]], G.NS);
     MSC_HIPCK(hipGetLastError());
@@ -751,6 +876,210 @@ class Solver : public SolverBase {
     double s = 0.0;
     for (int i = 0; i < nb; ++i) s += partials_h[i];
     return std::sqrt(s / ((double)Q * (double)G.NS));
+  }
+
+  // ------------------------------------------------------ adjoint pieces --
+  size_t record_bytes() const {
+    return 3 * sizeof(T) * (size_t)Q * G.NS + 2 * sizeof(double) * (size_t)(D + 1) * G.NS;
+  }
+
+  // Enqueue a copy of the current state (ctl_h must be current).
+  void take_checkpoint(int64_t bc) {
+    Record r{};
+    r.mem = dalloc(record_bytes());
+    r.bc = bc;
+    r.K = 0;
+    records.push_back(r);
+    const size_t fq = sizeof(T) * (size_t)Q * G.NS, fm = sizeof(double) * (size_t)(D + 1) * G.NS;
+    char* b = (char*)r.mem;
+    for (int i = 0; i < 3; ++i)
+      MSC_HIPCK(hipMemcpyAsync(b + i * fq, fb.p[ctl_h->slot_hist[i]], fq, hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < 2; ++i)
+      MSC_HIPCK(hipMemcpyAsync(b + 3 * fq + i * fm, mb[ctl_h->slot_m[i]], fm, hipMemcpyDeviceToDevice, st));
+  }
+
+  void drop_last_record() {
+    sync();
+    dfree(records.back().mem);
+    records.pop_back();
+  }
+
+  void clear_records() {
+    for (auto& r : records) dfree(r.mem);
+    records.clear();
+  }
+
+  void free_adjoint_buffers() {
+    for (void* p : adj_allocs) dfree(p);
+    adj_allocs.clear();
+    adj_lam[0] = adj_lam[1] = nullptr;
+    adj_LT = adj_LF = adj_carry = adj_lh = adj_h = nullptr;
+    adj_fT = adj_it = nullptr;
+    adj_it_cap = 0;
+    adj_y = adj_z = nullptr;
+    adj_x = XformBufs<double, double>{};
+  }
+
+  void ensure_adjoint_buffers(int K) {
+    const int64_t NS = G.NS, FQ = (int64_t)Q * NS, FM = (int64_t)(D + 1) * NS;
+    auto get = [&](size_t bytes) {
+      void* p = dalloc(bytes);
+      adj_allocs.push_back(p);
+      return p;
+    };
+    if (!adj_LT) {
+      for (int i = 0; i < 2; ++i) adj_lam[i] = (double*)get(sizeof(double) * state_size());
+      adj_LT = (double*)get(sizeof(double) * FQ);
+      adj_LF = (double*)get(sizeof(double) * FQ);
+      adj_carry = (double*)get(sizeof(double) * FQ);
+      adj_lh = (double*)get(sizeof(double) * FM);
+      adj_h = (double*)get(sizeof(double) * FM);
+      adj_fT = (double*)get(sizeof(double) * FQ);
+      adj_y = (double*)get(sizeof(double) * FM);
+      adj_z = (double*)get(sizeof(double) * FM);
+      if (P.corrector == MSC_CORRECTOR_SHADOW) {
+        adj_x.in = adj_y;
+        adj_x.out = adj_z;
+        if constexpr (std::is_same<CT, double>::value) {
+          adj_x.spec1 = spec;
+          adj_x.spec2 = spec2;
+          for (int i = 0; i < 3; ++i) adj_x.tw[i] = tw[i];
+        } else {
+          using C2 = cpx<double>;
+          if (D == 2) {
+            adj_x.spec1 = (C2*)get(sizeof(C2) * 3 * (size_t)G.N0 * (G.N2 / 4 + 1));
+            adj_x.tw[0] = make_twiddles<double>(G.N0, &adj_allocs);
+            adj_x.tw[2] = make_twiddles<double>(G.N2, &adj_allocs);
+          } else {
+            const int NBz = G.n[2] / 4 + 1, NBy = 2 * (G.n[1] / 4) + 1;
+            adj_x.spec1 = (C2*)get(sizeof(C2) * 4 * (size_t)G.n[0] * G.n[1] * NBz);
+            adj_x.spec2 = (C2*)get(sizeof(C2) * 4 * (size_t)G.n[0] * NBy * NBz);
+            for (int a = 0; a < 3; ++a) adj_x.tw[a] = make_twiddles<double>(G.n[a], &adj_allocs);
+          }
+          set_fft_attrs<double, double>();
+        }
+      }
+    }
+    if (K > adj_it_cap) {
+      adj_it = (double*)get(sizeof(double) * FQ * (size_t)K);
+      adj_it_cap = K;
+    }
+  }
+
+  // FP64 dual-time sweep of src into dst (diagnostic mode, no control
+  // block) for the recompute of the adjoint: P r into adj_y.
+  void sweep64(const double* src, double* dst, double a) {
+    SweepArgs<double, double> S{};
+    S.N0 = G.N0;
+    S.N1 = G.N1;
+    S.N2 = G.N2;
+    S.L = strip_L;
+    S.ntile1 = G.N1 / tile.T1;
+    S.ntile2 = G.N2 / tile.T2;
+    S.nstrip = G.N0 / strip_L;
+    S.NS = G.NS;
+    S.ctl = nullptr;
+    S.src = src;
+    S.dst = dst;
+    S.h = adj_h;
+    S.dm = adj_z;
+    S.Pr = adj_y;
+    S.partials = partials;
+    S.a = a;
+    S.inv1pa2 = 1.0 / (1.0 + a / 2.0);
+    S.wp = wp;
+    S.wm = wm;
+    if (D == 2)
+      launch_sweep_d2<double, double>(tile_id, SW_DTS, S, sweep_grid(), st);
+    else
+      launch_sweep_d3<double, double>(tile_id, SW_DTS, S, sweep_grid(), st);
+    MSC_HIPCK(hipGetLastError());
+  }
+
+  // Reverse one recorded step: recompute its inner iterates from the
+  // checkpoint, then run the transposed stages from the last sweep to the
+  // first and through the history combination.  lin is the adjoint of the
+  // state after the step, lout receives the adjoint of the state before it.
+  void backward_step(const Record& R, const double* lin, double* lout) {
+    const int64_t NS = G.NS, FQ = (int64_t)Q * NS, FM = (int64_t)(D + 1) * NS;
+    const bool shadow = (P.corrector == MSC_CORRECTOR_SHADOW);
+    const T* f0 = (const T*)R.mem;
+    const T* f1 = f0 + FQ;
+    const T* f2 = f0 + 2 * FQ;
+    const double* m0 = (const double*)((const char*)R.mem + 3 * sizeof(T) * (size_t)FQ);
+    const double* m1 = m0 + FM;
+    const int q = (R.bc == 0) ? 1 : 2;
+    const int max_order = (P.extrap_states == 0) ? 2 : P.extrap_states - 1;
+    const int order = (int)std::min<int64_t>(R.bc, max_order);
+    const double a = (q == 1) ? 1.0 / P.dt : 3.0 / (2.0 * P.dt);
+    const int K = R.K;
+    auto it = [&](int ell) { return adj_it + (size_t)(ell - 1) * FQ; };
+    const int eg = ew_grid();
+
+    // forward recompute of f^(1..K) in FP64
+    hipLaunchKernelGGL((k_extrap_h<T>), dim3(eg), dim3(256), 0, st, NS, Q, D + 1, order, q, P.dt, f0, f1, f2, m0,
+                       m1, it(1), adj_h);
+    MSC_HIPCK(hipGetLastError());
+    for (int ell = 1; ell < K; ++ell) {
+      sweep64(it(ell), shadow ? adj_fT : it(ell + 1), a);
+      if (shadow) {
+        enqueue_transform<double, double>(nullptr, 0, 0, a, nullptr, false, adj_x);
+        hipLaunchKernelGGL((k_lift<L, double, double>), dim3(eg), dim3(256), 0, st, (const double*)adj_fT,
+                           (const double*)adj_z, it(ell + 1), NS);
+        MSC_HIPCK(hipGetLastError());
+      }
+    }
+
+    // backward through the inner iterations
+    const double* lf0 = lin;
+    const double* lf1 = lin + FQ;
+    const double* lf2 = lin + 2 * FQ;
+    const double* lm0 = lin + 3 * FQ;
+    const double* lm1 = lin + 3 * FQ + FM;
+    double* LT = adj_LT;
+    double* LF = adj_LF;
+    hipLaunchKernelGGL((k_adj_seed<L>), dim3(eg), dim3(256), 0, st, NS, lf0, lm0, a, LT, adj_lh);
+    MSC_HIPCK(hipGetLastError());
+    const AdjGeom ag{G.N0, G.N1, G.N2, NS};
+    const double* carry = nullptr;
+    for (int ell = K; ell >= 1; --ell) {
+      hipLaunchKernelGGL((k_adj_sweep<L, double>), dim3(eg), dim3(256), 0, st, ag, (const double*)it(ell),
+                         (const double*)adj_h, (const double*)LT, carry, LF, adj_lh, a, wp, wm);
+      MSC_HIPCK(hipGetLastError());
+      if (ell == 1) break;
+      if (shadow) {
+        hipLaunchKernelGGL((k_adj_Et<L, double>), dim3(eg), dim3(256), 0, st, NS, (const double*)LF, adj_y);
+        MSC_HIPCK(hipGetLastError());
+        enqueue_transform<double, double>(nullptr, 0, 0, a, nullptr, true, adj_x);
+        hipLaunchKernelGGL((k_adj_lift<L, double>), dim3(eg), dim3(256), 0, st, NS, (const double*)adj_z,
+                           (const double*)LF, LT, adj_carry);
+        MSC_HIPCK(hipGetLastError());
+        carry = adj_carry;
+      } else {
+        std::swap(LT, LF);
+        carry = nullptr;
+      }
+    }
+    // LF holds the adjoint of the trial f^(1)
+    AdjSetupArgs A{};
+    A.NS = NS;
+    A.Q = Q;
+    A.D1 = D + 1;
+    A.order = order;
+    A.q = q;
+    A.dt = P.dt;
+    A.lf1n = lf1;
+    A.lf2n = lf2;
+    A.lm1n = lm1;
+    A.Lam1 = LF;
+    A.lam_h = adj_lh;
+    A.of0 = lout;
+    A.of1 = lout + FQ;
+    A.of2 = lout + 2 * FQ;
+    A.om0 = lout + 3 * FQ;
+    A.om1 = lout + 3 * FQ + FM;
+    hipLaunchKernelGGL(k_adj_setup<0>, dim3(eg), dim3(256), 0, st, A);
+    MSC_HIPCK(hipGetLastError());
   }
 
   // ------------------------------------------------------ sweep config --
@@ -988,8 +1317,7 @@ class Solver : public SolverBase {
   // FFT launch shapes
   // rows per block of the row passes: LDS-limited, and small enough that the
   // grid has >= 128 blocks when the grid is large enough
-  int fft_rows_per_block() const {
-    const size_t c = sizeof(cpx<CT>);
+  int fft_rows_per_block(size_t c = sizeof(cpx<CT>)) const {
     int R = (int)std::max<size_t>(1, (size_t)65536 / (4 * G.N2 * c));
     int p = 1;
     while (p * 2 <= R) p *= 2;
@@ -997,8 +1325,7 @@ class Solver : public SolverBase {
     return std::min(p, G.N0);
   }
   // columns per block of the column pass: LDS-limited, >= 64 blocks if possible
-  int fft_cols_per_block() const {
-    const size_t c = sizeof(cpx<CT>);
+  int fft_cols_per_block(size_t c = sizeof(cpx<CT>)) const {
     int J = (int)std::max<size_t>(1, (size_t)98304 / (6 * G.N0 * c));
     J = std::min(J, 16);
     const int NB = G.N2 / 4 + 1;
@@ -1008,73 +1335,81 @@ class Solver : public SolverBase {
 
   // 3D launch shapes: pencils per block of the z passes, j_z columns per
   // block of the y and x passes
-  int fft3_pencils_per_block() const {
-    const size_t c = sizeof(cpx<CT>);
+  int fft3_pencils_per_block(size_t c = sizeof(cpx<CT>)) const {
     int R = (int)std::max<size_t>(1, (size_t)65536 / (4 * G.n[2] * c));
     int p = 1;
     while (p * 2 <= R) p *= 2;
     while (p > 1 && ((int64_t)G.n[0] * G.n[1]) / p < 256) p >>= 1;
     return p;
   }
-  int fft3_cols_per_block() const {
-    const size_t c = sizeof(cpx<CT>);
+  int fft3_cols_per_block(size_t c = sizeof(cpx<CT>)) const {
     const int Nmax = std::max(G.n[0], G.n[1]);
     int J = (int)std::max<size_t>(1, (size_t)98304 / (8 * Nmax * c));
     J = std::min(J, 8);
     return std::max(J, 1);
   }
 
+  template <class CX = CT, class TX = TM>
   void set_fft_attrs() {
-    const size_t c = sizeof(cpx<CT>);
+    const size_t c = sizeof(cpx<CX>);
     if constexpr (D == 2) {
-      const int rows_b = (int)(4 * fft_rows_per_block() * G.N2 * c);
-      const int cols_b = (int)(6 * fft_cols_per_block() * G.N0 * c);
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_fwd<L, T, CT, TM>,
+      const int rows_b = (int)(4 * fft_rows_per_block(c) * G.N2 * c);
+      const int cols_b = (int)(6 * fft_cols_per_block(c) * G.N0 * c);
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_fwd<L, T, CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_inv<CT, TM>,
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_inv<CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_cols_solve<CT, TM>,
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_cols_solve<CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, cols_b));
     } else {
-      const int zb = (int)(4 * fft3_pencils_per_block() * G.n[2] * c);
+      const int zb = (int)(4 * fft3_pencils_per_block(c) * G.n[2] * c);
       const int Nmax = std::max(G.n[0], G.n[1]);
-      const int cb = (int)(8 * fft3_cols_per_block() * Nmax * c);
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_z_fwd<L, T, CT, TM>,
+      const int cb = (int)(8 * fft3_cols_per_block(c) * Nmax * c);
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_z_fwd<L, T, CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, zb));
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_z_inv<CT, TM>,
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_z_inv<CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, zb));
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_y_fwd<CT, TM>,
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_y_fwd<CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, cb));
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_y_inv<CT, TM>,
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_y_inv<CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, cb));
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_x_solve<CT, TM>,
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft3_x_solve<CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, cb));
     }
   }
+
 
   // The shadow correction of Eq. (shadow-update) for (step n, sweep ell):
   // transforms of P r, per-wavevector Schur solve, inverse transforms into dm
   // (the lift is fused into the next sweep).  With Ac the first pass instead
   // reconstructs m^{n+1} when the step was accepted at this sweep.
   void enqueue_correction(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac) {
+    XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
+    enqueue_transform<CT, TM>(c, n, ell, a, Ac, false, B);
+  }
+
+  template <class CX, class TX>
+  void enqueue_transform(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac, bool adjoint,
+                         const XformBufs<CX, TX>& B) {
     AcceptArgs<L, T> none{};
-    const size_t cb = sizeof(cpx<CT>);
+    const size_t cb = sizeof(cpx<CX>);
     if constexpr (D == 2) {
-      Fft2Args<CT, TM> F{};
+      Fft2Args<CX, TX> F{};
       F.g = CorrGuard{c, n, ell};
       F.do_accept = Ac ? 1 : 0;
+      F.adjoint = adjoint ? 1 : 0;
       F.Nx = G.N0;
       F.Ny = G.N2;
       F.lgx = ilog2(G.N0);
       F.lgy = ilog2(G.N2);
       F.NBy = G.N2 / 4 + 1;
-      F.rows_per_block = fft_rows_per_block();
-      F.cols_per_block = fft_cols_per_block();
-      F.Pr = Pr;
-      F.spec = spec;
-      F.dm = dm;
-      F.twx = tw[0];
-      F.twy = tw[2];
+      F.rows_per_block = fft_rows_per_block(cb);
+      F.cols_per_block = fft_cols_per_block(cb);
+      F.Pr = B.in;
+      F.spec = B.spec1;
+      F.dm = B.out;
+      F.twx = B.tw[0];
+      F.twy = B.tw[2];
       F.a = a;
       F.nu = nu;
       F.inv_ns = 1.0 / (double)G.NS;
@@ -1082,16 +1417,17 @@ class Solver : public SolverBase {
       const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
       const int grows = G.N0 / F.rows_per_block;
       const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
-      hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CT, TM>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none);
+      hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CX, TX>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft2_cols_solve<CT, TM>), dim3(gcols), dim3(256), cols_b, st, F);
+      hipLaunchKernelGGL((k_fft2_cols_solve<CX, TX>), dim3(gcols), dim3(256), cols_b, st, F);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft2_rows_inv<CT, TM>), dim3(grows), dim3(256), rows_b, st, F);
+      hipLaunchKernelGGL((k_fft2_rows_inv<CX, TX>), dim3(grows), dim3(256), rows_b, st, F);
       MSC_HIPCK(hipGetLastError());
     } else {
-      Fft3Args<CT, TM> F{};
+      Fft3Args<CX, TX> F{};
       F.g = CorrGuard{c, n, ell};
       F.do_accept = Ac ? 1 : 0;
+      F.adjoint = adjoint ? 1 : 0;
       F.Nx = G.n[0];
       F.Ny = G.n[1];
       F.Nz = G.n[2];
@@ -1100,15 +1436,15 @@ class Solver : public SolverBase {
       F.lgz = ilog2(F.Nz);
       F.NBz = F.Nz / 4 + 1;
       F.NBy = 2 * (F.Ny / 4) + 1;
-      F.pencils_per_block = fft3_pencils_per_block();
-      F.cols_per_block = fft3_cols_per_block();
-      F.Pr = Pr;
-      F.dm = dm;
-      F.spec1 = spec;
-      F.spec2 = spec2;
-      F.twx = tw[0];
-      F.twy = tw[1];
-      F.twz = tw[2];
+      F.pencils_per_block = fft3_pencils_per_block(cb);
+      F.cols_per_block = fft3_cols_per_block(cb);
+      F.Pr = B.in;
+      F.dm = B.out;
+      F.spec1 = B.spec1;
+      F.spec2 = B.spec2;
+      F.twx = B.tw[0];
+      F.twy = B.tw[1];
+      F.twz = B.tw[2];
       F.a = a;
       F.nu = nu;
       F.inv_ns = 1.0 / (double)G.NS;
@@ -1118,15 +1454,15 @@ class Solver : public SolverBase {
       const size_t xb = 8 * (size_t)JB * F.Nx * cb;
       const int ng = (F.NBz + JB - 1) / JB;
       const int gz = (int)(((int64_t)F.Nx * F.Ny) / R);
-      hipLaunchKernelGGL((k_fft3_z_fwd<L, T, CT, TM>), dim3(gz), dim3(256), zb, st, F, Ac ? *Ac : none);
+      hipLaunchKernelGGL((k_fft3_z_fwd<L, T, CX, TX>), dim3(gz), dim3(256), zb, st, F, Ac ? *Ac : none);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft3_y_fwd<CT, TM>), dim3(F.Nx * ng), dim3(256), yb, st, F);
+      hipLaunchKernelGGL((k_fft3_y_fwd<CX, TX>), dim3(F.Nx * ng), dim3(256), yb, st, F);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft3_x_solve<CT, TM>), dim3(F.NBy * ng), dim3(256), xb, st, F);
+      hipLaunchKernelGGL((k_fft3_x_solve<CX, TX>), dim3(F.NBy * ng), dim3(256), xb, st, F);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft3_y_inv<CT, TM>), dim3(F.Nx * ng), dim3(256), yb, st, F);
+      hipLaunchKernelGGL((k_fft3_y_inv<CX, TX>), dim3(F.Nx * ng), dim3(256), yb, st, F);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft3_z_inv<CT, TM>), dim3(gz), dim3(256), zb, st, F);
+      hipLaunchKernelGGL((k_fft3_z_inv<CX, TX>), dim3(gz), dim3(256), zb, st, F);
       MSC_HIPCK(hipGetLastError());
     }
   }

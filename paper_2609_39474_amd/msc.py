@@ -100,6 +100,10 @@ SIGNATURES = {
     "msc_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "msc_kernel_time": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int64), _dp]),
     "msc_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "msc_set_recording": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "msc_recorded_steps": (ctypes.c_int, [_vp, _ip]),
+    "msc_bdf2_adjoint": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int32]),
+    "msc_init_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32]),
 }
 
 _lib = None
@@ -111,6 +115,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime.  Importing it first makes the
+        # library bind to that same runtime (one runtime per process), so that
+        # torch streams and allocations are valid here and torch can still
+        # initialise the GPU after the library has used it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -172,6 +184,9 @@ class Solver:
     step failures that ``bdf2_step(..., raise_on_fail=False)`` returns."""
 
     def __init__(self, params: msc_params, phat0, u0, stream=None, torch_alloc=False):
+        """phat0, u0: host arrays, or device FP64 tensors (anything with
+        ``data_ptr``), which sets params.inputs_on_device: msc_moments then
+        writes device pointers too (``moments_device``)."""
         self.params = params
         self.d = 2 if params.lattice == MSC_D2Q9 else 3
         self.Q = 9 if self.d == 2 else 19
@@ -184,11 +199,20 @@ class Solver:
             ta = TorchAllocator()
             ta.install(params)
             self._keep.append(ta)
-        phat0 = _f64(phat0)
-        u0 = _f64(u0)
-        assert phat0.shape == self.shape and u0.shape == (self.d,) + self.shape
+        self.on_device = hasattr(phat0, "data_ptr")
+        if self.on_device:
+            assert tuple(phat0.shape) == self.shape and tuple(u0.shape) == (self.d,) + self.shape
+            assert phat0.is_contiguous() and u0.is_contiguous()
+            params.inputs_on_device = 1
+            p_ptr, u_ptr = phat0.data_ptr(), u0.data_ptr()
+        else:
+            params.inputs_on_device = 0
+            phat0 = _f64(phat0)
+            u0 = _f64(u0)
+            assert phat0.shape == self.shape and u0.shape == (self.d,) + self.shape
+            p_ptr, u_ptr = phat0.ctypes.data, u0.ctypes.data
         h = ctypes.c_void_p()
-        rc = lib().msc_init(ctypes.byref(params), phat0.ctypes.data, u0.ctypes.data, ctypes.byref(h))
+        rc = lib().msc_init(ctypes.byref(params), ctypes.c_void_p(p_ptr), ctypes.c_void_p(u_ptr), ctypes.byref(h))
         if rc != MSC_OK:
             raise MscError(rc, "msc_init")
         self.h = h
@@ -222,7 +246,14 @@ class Solver:
     def explicit_step(self, nsteps):
         self._check(lib().msc_explicit_step(self.h, int(nsteps)), "msc_explicit_step")
 
+    def moments_device(self, phat_ptr, u_ptr):
+        assert self.on_device
+        self._check(lib().msc_moments(self.h, ctypes.c_void_p(int(phat_ptr)), ctypes.c_void_p(int(u_ptr))),
+                    "msc_moments")
+
     def moments(self):
+        if self.on_device:
+            raise ValueError("context created from device inputs: use moments_device")
         m = np.zeros((self.d + 1,) + self.shape)
         self._check(lib().msc_moments(self.h, m.ctypes.data, m[1:].ctypes.data), "msc_moments")
         return m
@@ -273,10 +304,13 @@ class Solver:
         K = np.ascontiguousarray(K, dtype=np.int32)
         self._check(lib().msc_set_schedule(self.h, K.ctypes.data_as(_ip), len(K)), "msc_set_schedule")
 
-    def get_state(self):
+    def state_size(self):
         n = ctypes.c_int64()
         self._check(lib().msc_state_size(self.h, ctypes.byref(n)), "msc_state_size")
-        s = np.zeros(n.value)
+        return n.value
+
+    def get_state(self):
+        s = np.zeros(self.state_size())
         bc = ctypes.c_int64()
         self._check(lib().msc_get_state(self.h, _dptr(s), ctypes.byref(bc)), "msc_get_state")
         return s, bc.value
@@ -298,6 +332,38 @@ class Solver:
 
     def set_tuning(self, key, value):
         self._check(lib().msc_set_tuning(self.h, key, value), "msc_set_tuning")
+
+    # -- adjoint
+    def set_recording(self, on):
+        self._check(lib().msc_set_recording(self.h, 1 if on else 0), "msc_set_recording")
+
+    def recorded_steps(self):
+        n = ctypes.c_int32()
+        self._check(lib().msc_recorded_steps(self.h, ctypes.byref(n)), "msc_recorded_steps")
+        return n.value
+
+    def bdf2_adjoint(self, nsteps, lam):
+        """Host FP64 state-layout adjoint in, adjoint before the nsteps steps out."""
+        lam = np.array(lam, dtype=np.float64, copy=True)
+        self._check(lib().msc_bdf2_adjoint(self.h, int(nsteps), lam.ctypes.data, 0), "msc_bdf2_adjoint")
+        return lam
+
+    def bdf2_adjoint_device(self, nsteps, lam_ptr):
+        """In-place on a device FP64 buffer (pointer as int)."""
+        self._check(lib().msc_bdf2_adjoint(self.h, int(nsteps), ctypes.c_void_p(int(lam_ptr)), 1),
+                    "msc_bdf2_adjoint")
+
+    def init_adjoint(self, phat0, u0, lam):
+        phat0, u0, lam = _f64(phat0), _f64(u0), _f64(lam)
+        lp = np.zeros(self.shape)
+        lu = np.zeros((self.d,) + self.shape)
+        self._check(lib().msc_init_adjoint(self.h, phat0.ctypes.data, u0.ctypes.data, lam.ctypes.data,
+                                           lp.ctypes.data, lu.ctypes.data, 0), "msc_init_adjoint")
+        return lp, lu
+
+    def init_adjoint_device(self, phat0_ptr, u0_ptr, lam_ptr, lp_ptr, lu_ptr):
+        ptrs = [ctypes.c_void_p(int(p)) for p in (phat0_ptr, u0_ptr, lam_ptr, lp_ptr, lu_ptr)]
+        self._check(lib().msc_init_adjoint(self.h, *ptrs, 1), "msc_init_adjoint")
 
 
 def make_params(d, N, *, dt, eps, storage="fp64", corrector="shadow", tau_plus=1.0, tau_minus=1.0,

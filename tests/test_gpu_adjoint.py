@@ -1,0 +1,281 @@
+"""GPU discrete adjoint of the march (recorded checkpoints, msc_bdf2_adjoint,
+msc_init_adjoint, the torch.autograd.Function) against the FP64 CPU oracle's
+adjoint and against finite differences of the GPU march itself.
+
+Bars: FP64 storage, GPU adjoint vs oracle adjoint within 1e-10 relative (max
+norm); directional central finite differences (replayed inner counts) within
+1e-4 relative; FP32 storage adjoint vs FP64 adjoint for the same output
+adjoint within 1e-6 relative (the trajectories differ by the FP32 forward
+error; recompute and adjoint are FP64).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_39474_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NU = 1.0 / 6.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2609_39474_amd import msc
+    msc.lib()
+    return msc
+
+
+def _fields(shape, seed, U=None):
+    """Seeded divergence-free field on the smallest side, tiled periodically
+    to a non-cubic shape."""
+    d = len(shape)
+    N = min(shape)
+    if U is None:
+        U = 0.05 * NU * 16 / N
+    if d == 2:
+        p0, u0 = W.random_field_2d(N, U, seed=seed, jmax=min(4, N // 4))
+    else:
+        p0 = np.zeros((N,) * 3)
+        u0 = W.random_perturbation_3d(N, U, seed=seed, jmax=min(3, N // 4))
+    reps = tuple(n // N for n in shape)
+    return np.tile(p0, reps), np.tile(u0, (1,) + reps)
+
+
+def _solver(M, shape, p0, u0, *, dt, eps=1e-10, storage="fp64", corrector="shadow", extrap=0, n_min=None):
+    d = len(shape)
+    p = M.make_params(d, shape[0], dt=dt, eps=eps, storage=storage, corrector=corrector, extrap_states=extrap,
+                      n_min=n_min)
+    for a in range(d):
+        p.n[a] = shape[a]
+    return M.Solver(p, p0, u0)
+
+
+def _loss_grad(state, shape, ustar, Q):
+    """L = 1/2 |u^n - u*|^2 over the m^n velocity slot; returns (L, dL/dstate)."""
+    d = len(shape)
+    NS = int(np.prod(shape))
+    FQ = Q * NS
+    u = state[3 * FQ + NS:3 * FQ + (d + 1) * NS]
+    r = u - ustar.ravel()
+    lam = np.zeros_like(state)
+    lam[3 * FQ + NS:3 * FQ + (d + 1) * NS] = r
+    return 0.5 * float(r @ r), lam
+
+
+ORACLE_CASES = [
+    # shape, dt, corrector, extrap, nsteps
+    ((16, 16), 24.0, "shadow", 0, 4),
+    ((32, 16), 64.0, "shadow", 2, 5),
+    ((16, 32), 24.0, "picard", 0, 3),
+    ((8, 8, 8), 16.0, "shadow", 0, 3),
+    ((8, 16, 8), 16.0, "shadow", 2, 3),
+]
+
+
+@pytest.mark.parametrize("shape,dt,corr,extrap,nsteps", ORACLE_CASES)
+def test_adjoint_vs_oracle_fp64(M, orc, shape, dt, corr, extrap, nsteps):
+    say("adjoint vs oracle", shape, dt, corr, extrap, nsteps)
+    d = len(shape)
+    Q = 9 if d == 2 else 19
+    p0, u0 = _fields(shape, seed=11)
+    s = _solver(M, shape, p0, u0, dt=dt, corrector=corr, extrap=extrap)
+    st0, bc0 = s.get_state()
+    s.set_recording(True)
+    rc, stats = s.bdf2_step(nsteps)
+    assert rc == 0 and s.recorded_steps() == nsteps
+    K = [x["iters"] for x in stats]
+    st1, _ = s.get_state()
+    NS = int(np.prod(shape))
+    ustar = 0.5 * st1[3 * Q * NS + NS:3 * Q * NS + (d + 1) * NS]
+    _, lam = _loss_grad(st1, shape, ustar, Q)
+    g = s.bdf2_adjoint(nsteps, lam)
+    assert s.recorded_steps() == 0
+    kw = dict(dt=dt, eps=1e-10, corrector=1 if corr == "shadow" else 0, extrap_states=extrap,
+              nmin=2 if d == 2 else 1, kmax=300)
+    ref = orc.march_adjoint(st0, bc0, shape, lam, schedule=K, **kw)
+    e = rel(g, ref)
+    say("  K", K, "rel", e)
+    assert e <= 1e-10
+    s.close()
+
+
+def test_adjoint_split_calls_and_errors(M):
+    shape = (16, 16)
+    p0, u0 = _fields(shape, seed=3)
+    s = _solver(M, shape, p0, u0, dt=24.0)
+    s.set_recording(True)
+    s.bdf2_step(4)
+    st1, _ = s.get_state()
+    rng = np.random.default_rng(0)
+    lam = rng.normal(size=st1.shape)
+    with pytest.raises(M.MscError):
+        s.bdf2_adjoint(5, lam)
+    with pytest.raises(M.MscError):
+        s.bdf2_adjoint(0, lam)
+    one = s.bdf2_adjoint(4, lam)
+    # record again from the same start and reverse in two calls
+    s2 = _solver(M, shape, p0, u0, dt=24.0)
+    s2.set_recording(True)
+    s2.bdf2_step(4)
+    a = s2.bdf2_adjoint(1, lam)
+    assert s2.recorded_steps() == 3
+    two = s2.bdf2_adjoint(3, a)
+    assert rel(two, one) <= 1e-13
+    # recording off frees the records
+    s2.bdf2_step(1)
+    s2.set_recording(False)
+    assert s2.recorded_steps() == 0
+    s.close()
+    s2.close()
+
+
+def test_init_adjoint_vs_oracle(M, orc):
+    for shape in [(16, 32), (8, 8, 16)]:
+        say("init adjoint", shape)
+        p0, u0 = _fields(shape, seed=5)
+        p0 = p0 + 1e-3 * np.random.default_rng(1).normal(size=shape)
+        s = _solver(M, shape, p0, u0, dt=24.0)
+        lam = np.random.default_rng(2).normal(size=s.state_size())
+        lp, lu = s.init_adjoint(p0, u0, lam)
+        rp, ru = orc.initial_state_adjoint(p0, u0, lam)
+        assert rel(lp, rp) <= 1e-13 and rel(lu, ru) <= 1e-13
+        s.close()
+
+
+@pytest.mark.parametrize("shape,dt,corr", [((32, 32), 64.0, "shadow"), ((8, 8, 8), 16.0, "shadow"),
+                                           ((16, 16), 24.0, "picard")])
+def test_adjoint_finite_differences(M, shape, dt, corr):
+    """Directional central differences of the GPU march (FP64, replayed
+    inner counts) against <lam0, v>."""
+    say("adjoint FD", shape, dt, corr)
+    d = len(shape)
+    Q = 9 if d == 2 else 19
+    NS = int(np.prod(shape))
+    nsteps = 4
+    p0, u0 = _fields(shape, seed=7)
+    s = _solver(M, shape, p0, u0, dt=dt, corrector=corr)
+    st0, bc0 = s.get_state()
+    s.set_recording(True)
+    _, stats = s.bdf2_step(nsteps)
+    K = [x["iters"] for x in stats]
+    st1, _ = s.get_state()
+    ustar = 0.6 * st1[3 * Q * NS + NS:3 * Q * NS + (d + 1) * NS]
+    L1, lam = _loss_grad(st1, shape, ustar, Q)
+    g = s.bdf2_adjoint(nsteps, lam)
+    s.set_recording(False)
+
+    def L(state):
+        s.set_state(state, bc0)
+        s.set_schedule(K)
+        rc, _ = s.bdf2_step(nsteps)
+        assert rc == 0
+        st, _ = s.get_state()
+        return _loss_grad(st, shape, ustar, Q)[0]
+
+    rng = np.random.default_rng(9)
+    v = rng.normal(size=st0.shape) * np.abs(st0).max()
+    h = 1e-4
+    fd = (L(st0 + h * v) - L(st0 - h * v)) / (2 * h)
+    ad = float(g @ v)
+    say("  fd", fd, "ad", ad, "rel", abs(fd - ad) / abs(ad))
+    assert abs(fd - ad) <= 1e-4 * abs(ad)
+    s.close()
+
+
+def test_adjoint_fp32_vs_fp64(M):
+    """FP32 storage: checkpoints hold the FP32 trajectory, the recompute and
+    the adjoint are FP64.  With the same output adjoint the two adjoints
+    differ only through the trajectories (bar 1e-6).  Each run's own loss
+    gradient (u^n - u* from its own final state) differs by the FP32 forward
+    error, whose rough part reaches population modes outside the shadow band
+    that a few sweeps do not contract; that difference is measured and
+    bounded loosely (5e-3)."""
+    shape = (64, 64)
+    d, Q, NS = 2, 9, 64 * 64
+    nsteps = 5
+    p0, u0 = _fields(shape, seed=13)
+    U = slice(3 * Q * NS + NS, 3 * Q * NS + (d + 1) * NS)
+    s64 = _solver(M, shape, p0, u0, dt=64.0)
+    s64.set_recording(True)
+    _, stats = s64.bdf2_step(nsteps)
+    K = [x["iters"] for x in stats]
+    st64, _ = s64.get_state()
+    ustar = 0.5 * st64[U]
+    _, lam64 = _loss_grad(st64, shape, ustar, Q)
+
+    s32 = _solver(M, shape, p0, u0, dt=64.0, storage="fp32")
+    start32 = s32.get_state()
+    s32.set_schedule(K)
+    s32.set_recording(True)
+    s32.bdf2_step(nsteps)
+    st32, _ = s32.get_state()
+    _, lam32 = _loss_grad(st32, shape, ustar, Q)
+
+    def wrt_inputs(s, g):
+        return np.concatenate([a.ravel() for a in s.init_adjoint(p0, u0, g)])
+
+    ref = wrt_inputs(s64, s64.bdf2_adjoint(nsteps, lam64))
+    same = wrt_inputs(s32, s32.bdf2_adjoint(nsteps, lam64))
+    s32.set_state(*start32)
+    s32.set_schedule(K)
+    s32.bdf2_step(nsteps)
+    own = wrt_inputs(s32, s32.bdf2_adjoint(nsteps, lam32))
+    e_same, e_own = rel(same, ref), rel(own, ref)
+    say("FP32 vs FP64 adjoint wrt (p0, u0): same output adjoint", e_same, "; own loss gradient", e_own)
+    assert e_same <= 1e-6
+    assert e_own <= 5e-3
+    s64.close()
+    s32.close()
+
+
+def test_autograd_vorticity_control(M):
+    """The differentiable march from a vorticity control (Biot-Savart map in
+    torch, the march and its adjoint in the library): gradient against a
+    directional central difference at replayed inner counts."""
+    import torch
+
+    from paper_2609_39474_amd import autograd as AG
+
+    N, nsteps, dt = 64, 6, 64.0
+    dev = torch.device("cuda:0")
+    U = 0.05 * NU * 16 / N
+    w0 = torch.tensor(W.random_vorticity_2d(N, U, seed=1), device=dev)
+    wB = torch.tensor(W.random_vorticity_2d(N, U, seed=2), device=dev)
+    p = M.make_params(2, N, dt=dt, eps=1e-10)
+
+    def run(w, schedule=None, info=None):
+        u0 = AG.biot_savart(w)
+        ph0 = torch.zeros((N, N), dtype=torch.float64, device=dev)
+        return AG.march(ph0, u0, p, nsteps, schedule=schedule, info=info)
+
+    with torch.no_grad():
+        _, ustar = run(wB)
+    w = w0.clone().requires_grad_(True)
+    info = {}
+    _, u = run(w, info=info)
+    loss = 0.5 * ((u - ustar) ** 2).sum()
+    loss.backward()
+    K = info["schedule"]
+    g = w.grad.detach()
+    v = torch.tensor(np.random.default_rng(3).normal(size=(N, N)), device=dev)
+    v *= w0.norm() / v.norm()
+    h = 1e-3
+    with torch.no_grad():
+        Lp = 0.5 * ((run(w0 + h * v, schedule=K)[1] - ustar) ** 2).sum().item()
+        Lm = 0.5 * ((run(w0 - h * v, schedule=K)[1] - ustar) ** 2).sum().item()
+    fd = (Lp - Lm) / (2 * h)
+    ad = float((g * v).sum())
+    say("autograd: K", K, "fd", fd, "ad", ad, "rel", abs(fd - ad) / abs(ad))
+    assert abs(fd - ad) <= 1e-4 * abs(ad)
