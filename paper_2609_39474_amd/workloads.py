@@ -200,6 +200,12 @@ def config(name: str):
         T_end, S, dt = horizon(0.1, N, nu, 64.0)
         return dict(name=name, d=3, N=N, Re=Re, U=Re * nu / N, nu=nu, T_end=T_end, S=S, dt=dt,
                     eps=1e-8, nmin=1, storage="fp32", kind="tgv3d_pert", seed=1)
+    if name == "vort2d_n256_adjoint":
+        # differentiable march: vorticity control (seed 1), target from the
+        # march of the seed-2 control, 20 steps of dt = 64
+        N, Re = 256, 1.0
+        return dict(name=name, d=2, N=N, Re=Re, U=Re * nu / N, nu=nu, nsteps=20, dt=64.0, T_end=20 * 64.0,
+                    eps=1e-8, nmin=2, storage="fp32", kind="vort2d", seed=1, target_seed=2)
     raise KeyError(name)
 
 

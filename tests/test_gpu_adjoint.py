@@ -279,3 +279,60 @@ def test_autograd_vorticity_control(M):
     ad = float((g * v).sum())
     say("autograd: K", K, "fd", fd, "ad", ad, "rel", abs(fd - ad) / abs(ad))
     assert abs(fd - ad) <= 1e-4 * abs(ad)
+
+
+def test_adjoint_vorticity_control_n256(M):
+    """Vorticity control at N = 256: 20 steps of dt = 64 from the seed-1
+    vorticity, loss against the 20-step endpoint of the seed-2 vorticity.
+    FP64: eight directional central differences (h = 1e-3 relative, replayed
+    inner counts) within 1e-4.  FP32 storage (same counts): gradient error
+    relative to FP64 measured and bounded (5e-3 in the max norm; it is the
+    FP32 forward's error carried by the loss gradient, see the FP32 test
+    above)."""
+    import torch
+
+    from paper_2609_39474_amd import autograd as AG
+
+    cfg = W.config("vort2d_n256_adjoint")
+    N, nsteps, dt, U = cfg["N"], cfg["nsteps"], cfg["dt"], cfg["U"]
+    dev = torch.device("cuda:0")
+    w0 = torch.tensor(W.random_vorticity_2d(N, U, seed=cfg["seed"]), device=dev)
+    wB = torch.tensor(W.random_vorticity_2d(N, U, seed=cfg["target_seed"]), device=dev)
+    zero = torch.zeros((N, N), dtype=torch.float64, device=dev)
+
+    def run(w, storage, schedule=None, info=None):
+        p = M.make_params(2, N, dt=dt, eps=cfg["eps"], storage=storage)
+        return AG.march(zero, AG.biot_savart(w), p, nsteps, schedule=schedule, info=info)[1]
+
+    with torch.no_grad():
+        ustar = run(wB, "fp64")
+    grads = {}
+    K = None
+    for storage in ("fp64", "fp32"):
+        w = w0.clone().requires_grad_(True)
+        info = {}
+        u = run(w, storage, schedule=K, info=info)
+        if K is None:
+            K = info["schedule"]
+        (0.5 * ((u - ustar) ** 2).sum()).backward()
+        grads[storage] = w.grad.detach().clone()
+    say("n256 adjoint: K", K)
+    g = grads["fp64"]
+    rng = np.random.default_rng(4)
+    h = 1e-3
+    worst = 0.0
+    for i in range(8):
+        v = torch.tensor(rng.normal(size=(N, N)), device=dev)
+        v *= w0.norm() / v.norm()
+        with torch.no_grad():
+            Lp = 0.5 * ((run(w0 + h * v, "fp64", schedule=K) - ustar) ** 2).sum().item()
+            Lm = 0.5 * ((run(w0 - h * v, "fp64", schedule=K) - ustar) ** 2).sum().item()
+        fd = (Lp - Lm) / (2 * h)
+        ad = float((g * v).sum())
+        worst = max(worst, abs(fd - ad) / abs(ad))
+        say("  dir", i, "fd", fd, "ad", ad)
+    e32 = float((grads["fp32"] - g).abs().max() / g.abs().max())
+    e32_l2 = float((grads["fp32"] - g).norm() / g.norm())
+    say("  worst FD rel", worst, "; FP32 gradient rel error: max-norm", e32, "L2", e32_l2)
+    assert worst <= 1e-4
+    assert e32 <= 5e-3
