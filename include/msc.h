@@ -63,7 +63,13 @@ typedef enum msc_storage {
   MSC_STORAGE_FP64 = 0, /* FP64 populations, FP64 arithmetic */
   MSC_STORAGE_FP32 = 1, /* FP32 populations and arithmetic; FP64 BDF history
                            combination, residual reductions and per-wavevector solve */
-  MSC_STORAGE_FP16_DEV = 2 /* FP16 deviation from equilibrium plus FP32 moments */
+  MSC_STORAGE_FP16_DEV = 2 /* populations as g = (f - feq(P f))/sigma in FP16 plus P f in
+                              FP32, sigma a power of two chosen from the data when a state
+                              is set (msc_init, msc_set_populations, msc_set_state); FP32
+                              arithmetic as MSC_STORAGE_FP32.  The rebuild keeps P f equal
+                              to the stored moments; the raw residual is taken against the
+                              stored output.  A deviation beyond the FP16 range becomes
+                              non-finite and fails the step (MSC_ERR_NONFINITE) */
 } msc_storage;
 
 typedef struct msc_params {

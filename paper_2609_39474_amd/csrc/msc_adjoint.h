@@ -226,25 +226,31 @@ __global__ void k_adj_setup(AdjSetupArgs A) {
 
 // Forward recompute helpers: the trial by extrapolation and h_q (Eq. bdf2),
 // from checkpointed populations of type T into FP64 iterates.
-template <class T>
-__global__ void k_extrap_h(int64_t NS, int Q, int D1, int order, int q, double dt, const T* __restrict__ f0,
+template <class L, class T>
+__global__ void k_extrap_h(int64_t NS, int order, int q, double dt, const T* __restrict__ f0,
                            const T* __restrict__ f1, const T* __restrict__ f2, const double* __restrict__ mc,
-                           const double* __restrict__ mp, double* __restrict__ trial, double* __restrict__ h) {
-  using CT = double;
+                           const double* __restrict__ mp, float sig, double* __restrict__ trial,
+                           double* __restrict__ h) {
+  using CT = typename CompT<T>::type;
+  constexpr int Q = L::Q, D1 = L::D + 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
     for (int b = 0; b < D1; ++b)
       h[b * NS + s] = (q == 1) ? mc[b * NS + s] / dt : (4.0 * mc[b * NS + s] - mp[b * NS + s]) / (2.0 * dt);
+    CT a0[Q], a1[Q], a2[Q];
+    site_load<L, T>(f0, NS, s, sig, a0);
+    if (order >= 1) site_load<L, T>(f1, NS, s, sig, a1);
+    if (order >= 2) site_load<L, T>(f2, NS, s, sig, a2);
+#pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const int64_t i = (int64_t)k * NS + s;
-      CT v;
+      double v;
       if (order == 0)
-        v = (CT)f0[i];
+        v = (double)a0[k];
       else if (order == 1)
-        v = (CT)2 * (CT)f0[i] - (CT)f1[i];
+        v = 2.0 * (double)a0[k] - (double)a1[k];
       else
-        v = (CT)3 * (CT)f0[i] - (CT)3 * (CT)f1[i] + (CT)f2[i];
-      trial[i] = v;
+        v = 3.0 * (double)a0[k] - 3.0 * (double)a1[k] + (double)a2[k];
+      trial[(int64_t)k * NS + s] = v;
     }
   }
 }

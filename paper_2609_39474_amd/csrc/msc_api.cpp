@@ -73,7 +73,6 @@ msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, 
   if (p->storage != MSC_STORAGE_FP64 && p->storage != MSC_STORAGE_FP32 &&
       p->storage != MSC_STORAGE_FP16_DEV)
     return MSC_ERR_INVALID_ARG;
-  if (p->storage == MSC_STORAGE_FP16_DEV) return MSC_ERR_UNSUPPORTED;
 
   msc_ctx* c = new (std::nothrow) msc_ctx();
   if (!c) return MSC_ERR_OUT_OF_MEMORY;
@@ -102,11 +101,21 @@ msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, 
     }
     c->own_stream = true;
   }
-  const bool fp64 = (p->storage == MSC_STORAGE_FP64);
-  if (d == 2)
-    c->s = fp64 ? msc::make_solver_d2_fp64(*p, g, c->stream) : msc::make_solver_d2_fp32(*p, g, c->stream);
-  else
-    c->s = fp64 ? msc::make_solver_d3_fp64(*p, g, c->stream) : msc::make_solver_d3_fp32(*p, g, c->stream);
+  if (d == 2) {
+    if (p->storage == MSC_STORAGE_FP64)
+      c->s = msc::make_solver_d2_fp64(*p, g, c->stream);
+    else if (p->storage == MSC_STORAGE_FP32)
+      c->s = msc::make_solver_d2_fp32(*p, g, c->stream);
+    else
+      c->s = msc::make_solver_d2_fp16dev(*p, g, c->stream);
+  } else {
+    if (p->storage == MSC_STORAGE_FP64)
+      c->s = msc::make_solver_d3_fp64(*p, g, c->stream);
+    else if (p->storage == MSC_STORAGE_FP32)
+      c->s = msc::make_solver_d3_fp32(*p, g, c->stream);
+    else
+      c->s = msc::make_solver_d3_fp16dev(*p, g, c->stream);
+  }
   if (!c->s) {
     msc_free(c);
     return MSC_ERR_OUT_OF_MEMORY;

@@ -111,4 +111,80 @@ struct FBufs {
   T* p[5];
 };
 
+// ------------------------------------------- FP16 deviation storage --
+// A buffer of element type _Float16 holds populations as their deviation
+// from equilibrium: g[k*NS + s] = (f_k - feq_k(M)) / sigma in FP16, followed
+// by the moments M = P f as FP32, M[b*NS + s] (starting at element Q*NS).
+// sigma is a power of two fixed per state.  The rebuild projects the FP16
+// rounding of g out of the conserved moments, so that P f = M exactly:
+// g' = g - w_k (sum g + 3 c_k . sum c g) (sum w = 1, sum w c = 0,
+// sum w c c = I/3).
+template <class T>
+struct PopDev {
+  static constexpr bool value = false;
+};
+template <>
+struct PopDev<_Float16> {
+  static constexpr bool value = true;
+};
+
+template <class T>
+__host__ __device__ inline float* dev_moments(T* p, int Q, int64_t NS) {
+  return reinterpret_cast<float*>(p + (int64_t)Q * NS);
+}
+template <class T>
+__host__ __device__ inline const float* dev_moments(const T* p, int Q, int64_t NS) {
+  return reinterpret_cast<const float*>(p + (int64_t)Q * NS);
+}
+
+// Equilibrium (Eq. feq) in FP32 from moments M = (p, u).
+template <class L>
+__device__ inline float feq_f32(int k, const float* M) {
+  float cu = 0.f, uu = 0.f;
+#pragma unroll
+  for (int b = 0; b < L::D; ++b) {
+    cu += (float)ca<L>(k, b) * M[1 + b];
+    uu += M[1 + b] * M[1 + b];
+  }
+  return (float)L::w(k) * (M[0] + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
+}
+
+// f from (g, M).
+template <class L>
+__device__ inline void dev_rebuild(const _Float16* g, const float* M, float sig, float* f) {
+  float gs[L::Q], s0 = 0.f, s1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    gs[k] = (float)g[k];
+    s0 += gs[k];
+#pragma unroll
+    for (int b = 0; b < L::D; ++b)
+      if (ca<L>(k, b) != 0) s1[b] += (float)ca<L>(k, b) * gs[k];
+  }
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    float cs = 0.f;
+#pragma unroll
+    for (int b = 0; b < L::D; ++b)
+      if (ca<L>(k, b) != 0) cs += (float)ca<L>(k, b) * s1[b];
+    f[k] = feq_f32<L>(k, M) + sig * (gs[k] - (float)L::w(k) * (s0 + 3.f * cs));
+  }
+}
+
+// (g, M) from f.
+template <class L>
+__device__ inline void dev_split(const float* f, float isig, _Float16* g, float* M) {
+#pragma unroll
+  for (int b = 0; b <= L::D; ++b) M[b] = 0.f;
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    M[0] += f[k];
+#pragma unroll
+    for (int b = 0; b < L::D; ++b)
+      if (ca<L>(k, b) != 0) M[1 + b] += (float)ca<L>(k, b) * f[k];
+  }
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) g[k] = (_Float16)((f[k] - feq_f32<L>(k, M)) * isig);
+}
+
 }  // namespace msc

@@ -19,13 +19,17 @@ struct AcceptArgs {
   double a;
 };
 
+// P f in FP64 at one site (for deviation storage the stored moments, which
+// the rebuild preserves exactly).
 template <class L, class T>
-__device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64_t s1, int64_t stride) {
-  const T* f = A.fb.p[A.ctl->slot_hist[0]];
-  double* m = A.mb[A.ctl->slot_m[0]];
-  const int64_t NS = A.NS;
-  for (int64_t s = s0; s < s1; s += stride) {
-    double M[4] = {0, 0, 0, 0};
+__device__ inline void site_moments(const T* f, int64_t NS, int64_t s, double* M) {
+  if constexpr (PopDev<T>::value) {
+    const float* Ms = dev_moments(f, L::Q, NS);
+#pragma unroll
+    for (int b = 0; b <= L::D; ++b) M[b] = (double)Ms[b * NS + s];
+  } else {
+#pragma unroll
+    for (int b = 0; b <= L::D; ++b) M[b] = 0.0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
       const double v = (double)f[(int64_t)k * NS + s];
@@ -34,6 +38,52 @@ __device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64
       for (int b = 0; b < L::D; ++b)
         if (ca<L>(k, b) != 0) M[1 + b] += (double)ca<L>(k, b) * v;
     }
+  }
+}
+
+// All Q populations of one site in the compute type.
+template <class L, class T>
+__device__ inline void site_load(const T* f, int64_t NS, int64_t s, float sig, typename CompT<T>::type* v) {
+  if constexpr (PopDev<T>::value) {
+    _Float16 g[L::Q];
+    float M[L::D + 1];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) g[k] = f[(int64_t)k * NS + s];
+    const float* Ms = dev_moments(f, L::Q, NS);
+#pragma unroll
+    for (int b = 0; b <= L::D; ++b) M[b] = Ms[b * NS + s];
+    dev_rebuild<L>(g, M, sig, v);
+  } else {
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) v[k] = (typename CompT<T>::type)f[(int64_t)k * NS + s];
+  }
+}
+
+template <class L, class T>
+__device__ inline void site_store(T* f, int64_t NS, int64_t s, float isig, const typename CompT<T>::type* v) {
+  if constexpr (PopDev<T>::value) {
+    _Float16 g[L::Q];
+    float M[L::D + 1];
+    dev_split<L>(v, isig, g, M);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) f[(int64_t)k * NS + s] = g[k];
+    float* Ms = dev_moments(f, L::Q, NS);
+#pragma unroll
+    for (int b = 0; b <= L::D; ++b) Ms[b * NS + s] = M[b];
+  } else {
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) f[(int64_t)k * NS + s] = (T)v[k];
+  }
+}
+
+template <class L, class T>
+__device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64_t s1, int64_t stride) {
+  const T* f = A.fb.p[A.ctl->slot_hist[0]];
+  double* m = A.mb[A.ctl->slot_m[0]];
+  const int64_t NS = A.NS;
+  for (int64_t s = s0; s < s1; s += stride) {
+    double M[4];
+    site_moments<L, T>(f, NS, s, M);
 #pragma unroll
     for (int b = 0; b <= L::D; ++b) m[b * NS + s] = (M[b] + A.h[b * NS + s] / 2.0) / (1.0 + A.a / 2.0);
   }
@@ -47,10 +97,22 @@ __global__ void k_accept(AcceptArgs<L, T> A) {
 
 // ------------------------------------------------------ initialisation --
 // f = feq(p, u) (Eq. feq) from FP64 fields; the initial state of Sec. 4.1.
+// Deviation storage: g = 0 and M = (p, u) (P feq(p, u) = (p, u)).
 template <class L, class T>
 __global__ void k_init_feq(const double* __restrict__ p, const double* __restrict__ u, T* __restrict__ f,
                            int64_t NS) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if constexpr (PopDev<T>::value) {
+    float* M = dev_moments(f, L::Q, NS);
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
+#pragma unroll
+      for (int k = 0; k < L::Q; ++k) f[(int64_t)k * NS + s] = (_Float16)0.f;
+      M[s] = (float)p[s];
+#pragma unroll
+      for (int b = 0; b < L::D; ++b) M[(1 + b) * NS + s] = (float)u[b * NS + s];
+    }
+    return;
+  }
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
     double m[4] = {p[s], 0, 0, 0};
     double uu = 0;
@@ -77,15 +139,8 @@ template <class L, class T>
 __global__ void k_moments(const T* __restrict__ f, double* __restrict__ m, int64_t NS) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
-    double M[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < L::Q; ++k) {
-      const double v = (double)f[(int64_t)k * NS + s];
-      M[0] += v;
-#pragma unroll
-      for (int b = 0; b < L::D; ++b)
-        if (ca<L>(k, b) != 0) M[1 + b] += (double)ca<L>(k, b) * v;
-    }
+    double M[4];
+    site_moments<L, T>(f, NS, s, M);
 #pragma unroll
     for (int b = 0; b <= L::D; ++b) m[b * NS + s] = M[b];
   }
@@ -94,8 +149,8 @@ __global__ void k_moments(const T* __restrict__ f, double* __restrict__ m, int64
 // out = fT + E dm (Eq. lift, Eq. shadow-update) with the same arithmetic the
 // sweep applies when it fuses the lift into its load.
 template <class L, class T, class TM>
-__global__ void k_lift(const T* __restrict__ fT, const TM* __restrict__ dm, T* __restrict__ out,
-                       int64_t NS) {
+__global__ void k_lift(const T* __restrict__ fT, const TM* __restrict__ dm, T* __restrict__ out, int64_t NS,
+                       float sig, float isig) {
   using CT = typename CompT<T>::type;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
@@ -103,13 +158,89 @@ __global__ void k_lift(const T* __restrict__ fT, const TM* __restrict__ dm, T* _
     CT du[3] = {0, 0, 0};
 #pragma unroll
     for (int b = 0; b < L::D; ++b) du[b] = (CT)dm[(1 + b) * NS + s];
+    CT v[L::Q];
+    site_load<L, T>(fT, NS, s, sig, v);
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
       CT cu = 0;
 #pragma unroll
       for (int b = 0; b < L::D; ++b) cu += (CT)ca<L>(k, b) * du[b];
-      out[(int64_t)k * NS + s] = (T)((CT)fT[(int64_t)k * NS + s] + (CT)L::w(k) * (d0 + (CT)3 * cu));
+      v[k] = v[k] + (CT)L::w(k) * (d0 + (CT)3 * cu);
     }
+    site_store<L, T>(out, NS, s, isig, v);
+  }
+}
+
+// Populations between the storage type and FP64 (canonical layout).
+template <class L, class T>
+__global__ void k_pop_to_f64(const T* __restrict__ in, double* __restrict__ out, int64_t NS, float sig) {
+  using CT = typename CompT<T>::type;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
+    CT v[L::Q];
+    site_load<L, T>(in, NS, s, sig, v);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) out[(int64_t)k * NS + s] = (double)v[k];
+  }
+}
+
+template <class L, class T>
+__global__ void k_pop_from_f64(const double* __restrict__ in, T* __restrict__ out, int64_t NS, float isig) {
+  using CT = typename CompT<T>::type;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
+    CT v[L::Q];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) v[k] = (CT)in[(int64_t)k * NS + s];
+    site_store<L, T>(out, NS, s, isig, v);
+  }
+}
+
+// Per-block maxima of |f_k - feq_k(P f)| and of |P f| over FP64 populations:
+// partials[2 b] and partials[2 b + 1] (the scale choice of deviation storage).
+template <class L>
+__global__ __launch_bounds__(256) void k_pop_maxdev(const double* __restrict__ f, int64_t NS,
+                                                    double* __restrict__ partials) {
+  __shared__ double r0[256], r1[256];
+  double md = 0.0, mm = 0.0;
+  const double cs2 = 1.0 / 3.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
+    double M[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      const double v = f[(int64_t)k * NS + s];
+      M[0] += v;
+#pragma unroll
+      for (int b = 0; b < L::D; ++b) M[1 + b] += (double)ca<L>(k, b) * v;
+    }
+    double uu = 0.0;
+#pragma unroll
+    for (int b = 0; b <= L::D; ++b) mm = fmax(mm, fabs(M[b]));
+#pragma unroll
+    for (int b = 0; b < L::D; ++b) uu += M[1 + b] * M[1 + b];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+      double cu = 0.0;
+#pragma unroll
+      for (int b = 0; b < L::D; ++b) cu += (double)ca<L>(k, b) * M[1 + b];
+      const double fe = L::w(k) * (M[0] + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+      md = fmax(md, fabs(f[(int64_t)k * NS + s] - fe));
+    }
+  }
+  r0[threadIdx.x] = md;
+  r1[threadIdx.x] = mm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + w]);
+      r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = r0[0];
+    partials[2 * blockIdx.x + 1] = r1[0];
   }
 }
 
@@ -117,6 +248,22 @@ template <class A, class B>
 __global__ void k_convert(const A* __restrict__ in, B* __restrict__ out, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = (B)in[i];
+}
+
+// Per-block maxima of |v|.
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_absmax(const double* __restrict__ v, int64_t n, double* partials) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc = fmax(acc, fabs(v[i]));
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
 // Per-block partial sums of v^2 (a non-finite entry makes the sum non-finite).

@@ -69,5 +69,7 @@ SolverBase* make_solver_d2_fp64(const msc_params& p, const Geometry& g, hipStrea
 SolverBase* make_solver_d2_fp32(const msc_params& p, const Geometry& g, hipStream_t s);
 SolverBase* make_solver_d3_fp64(const msc_params& p, const Geometry& g, hipStream_t s);
 SolverBase* make_solver_d3_fp32(const msc_params& p, const Geometry& g, hipStream_t s);
+SolverBase* make_solver_d2_fp16dev(const msc_params& p, const Geometry& g, hipStream_t s);
+SolverBase* make_solver_d3_fp16dev(const msc_params& p, const Geometry& g, hipStream_t s);
 
 }  // namespace msc

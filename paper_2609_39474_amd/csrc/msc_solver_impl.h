@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -108,6 +109,7 @@ class Solver : public SolverBase {
   using CT = typename CompT<T>::type;
   using TM = CT;
   static constexpr int Q = L::Q, D = L::D;
+  static constexpr bool DV = PopDev<T>::value;  // FP16 deviation storage
 
   Solver(const msc_params& p, const Geometry& g, hipStream_t s) : P(p), G(g), st(s) {
     wp = 1.0 / P.tau_plus;
@@ -160,6 +162,7 @@ class Solver : public SolverBase {
       ctl_h->slot_w[1] = 4;
       for (int i = 0; i < 3; ++i) ctl_h->slot_m[i] = i;
       MSC_HIPCK(hipMemcpyAsync(ctl, ctl_h, sizeof(DevCtl), hipMemcpyHostToDevice, st));
+      if (DV) sig = choose_sigma(0.0, std::max(absmax(pd, NS), absmax(ud, (int64_t)D * NS)));
       hipLaunchKernelGGL((k_init_feq<L, T>), dim3(ew_grid()), dim3(256), 0, st, pd, ud, fb.p[0], NS);
       MSC_HIPCK(hipGetLastError());
       reset_history_from_current();
@@ -284,7 +287,7 @@ class Solver : public SolverBase {
       MSC_HIPCK(hipMemcpyAsync(ctl, ctl_h, sizeof(DevCtl), hipMemcpyHostToDevice, st));
       reset_history_from_current();
       // non-finite check on the final state
-      const double ss = sumsq(fb.p[ctl_h->slot_hist[0]], (int64_t)Q * G.NS);
+      const double ss = pop_sumsq(fb.p[ctl_h->slot_hist[0]]);
       if (!std::isfinite(ss)) {
         last_error = "non-finite population after the explicit march";
         return MSC_ERR_NONFINITE;
@@ -337,6 +340,7 @@ class Solver : public SolverBase {
   msc_status set_populations(const double* f) override {
     return guard([&]() {
       pull_ctl();
+      if (DV) sig = sigma_for({f});
       upload_pop(f, fb.p[ctl_h->slot_hist[0]]);
       reset_history_from_current();
       sync();
@@ -351,6 +355,8 @@ class Solver : public SolverBase {
       pull_ctl();
       T* A = fb.p[ctl_h->slot_w[0]];
       T* B = fb.p[ctl_h->slot_w[1]];
+      const float sig_state = sig;  // the work buffers may take another scale
+      if (DV) sig = sigma_for({f});
       upload_pop(f, A);
       upload_h(h_in);
       SweepArgs<T, TM> S = sweep_args(a);
@@ -362,6 +368,7 @@ class Solver : public SolverBase {
       if (fT) download_pop(B, fT);
       if (Pr_out) download_tm(Pr, Pr_out, (int64_t)(D + 1) * G.NS);
       sync();
+      sig = sig_state;
       return MSC_OK;
     });
   }
@@ -376,6 +383,8 @@ class Solver : public SolverBase {
       pull_ctl();
       T* A = fb.p[ctl_h->slot_w[0]];
       T* B = fb.p[ctl_h->slot_w[1]];
+      const float sig_state = sig;
+      if (DV) sig = sigma_for({f});
       upload_pop(f, A);
       upload_h(h_in);
       SweepArgs<T, TM> S = sweep_args(a);
@@ -388,11 +397,12 @@ class Solver : public SolverBase {
       // f_next = f_T + E dm: the same lift the next sweep applies on load,
       // here through an explicit no-op-collision pass is not available, so
       // apply it element-wise.
-      hipLaunchKernelGGL((k_lift<L, T, TM>), dim3(ew_grid()), dim3(256), 0, st, B, dm, A, G.NS);
+      hipLaunchKernelGGL((k_lift<L, T, TM>), dim3(ew_grid()), dim3(256), 0, st, B, dm, A, G.NS, sig, 1.0f / sig);
       MSC_HIPCK(hipGetLastError());
       if (fnext) download_pop(A, fnext);
       if (dm_out) download_tm(dm, dm_out, (int64_t)(D + 1) * G.NS);
       sync();
+      sig = sig_state;
       return MSC_OK;
     });
   }
@@ -436,6 +446,7 @@ class Solver : public SolverBase {
     return guard([&]() {
       pull_ctl();
       const int64_t FQ = (int64_t)Q * G.NS, FM = (int64_t)(D + 1) * G.NS;
+      if (DV) sig = sigma_for({state, state + FQ, state + 2 * FQ});
       for (int i = 0; i < 3; ++i) upload_pop(state + i * FQ, fb.p[ctl_h->slot_hist[i]]);
       MSC_HIPCK(hipMemcpyAsync(mb[ctl_h->slot_m[0]], state + 3 * FQ, sizeof(double) * FM,
                                hipMemcpyHostToDevice, st));
@@ -582,6 +593,7 @@ class Solver : public SolverBase {
   int n_next = 0;
   int64_t bdf_count = 0;
   int last_iters = 4;
+  float sig = 1.0f;  // scale of FP16 deviation storage (unused otherwise)
 
   // explicit-march graph cache
   hipGraphExec_t gexec = nullptr;
@@ -609,9 +621,10 @@ class Solver : public SolverBase {
 
   // adjoint records and buffers
   struct Record {
-    void* mem;   // f^n, f^{n-1}, f^{n-2} (T), then m^n, m^{n-1} (FP64)
+    void* mem;   // f^n, f^{n-1}, f^{n-2} (storage format), then m^n, m^{n-1} (FP64)
     int64_t bc;  // BDF steps accepted before this step
     int K;       // inner sweeps at acceptance; 0 while the step is in flight
+    float sig;   // deviation-storage scale of the checkpointed populations
   };
   bool recording = false;
   std::vector<Record> records;
@@ -692,7 +705,7 @@ class Solver : public SolverBase {
 
   void allocate() {
     const int64_t NS = G.NS;
-    const size_t fbytes = sizeof(T) * Q * NS;
+    const size_t fbytes = pop_bytes();
     for (int i = 0; i < 5; ++i) fb.p[i] = keep((T*)dalloc(fbytes));
     for (int i = 0; i < 3; ++i) mb[i] = keep((double*)dalloc(sizeof(double) * (D + 1) * NS));
     h = keep((double*)dalloc(sizeof(double) * (D + 1) * NS));
@@ -817,7 +830,7 @@ class Solver : public SolverBase {
   // (next step BDF1, whose trial uses f^n alone).
   void reset_history_from_current() {
     for (int i = 1; i < 3; ++i)
-      MSC_HIPCK(hipMemcpyAsync(fb.p[ctl_h->slot_hist[i]], fb.p[ctl_h->slot_hist[0]], sizeof(T) * Q * G.NS,
+      MSC_HIPCK(hipMemcpyAsync(fb.p[ctl_h->slot_hist[i]], fb.p[ctl_h->slot_hist[0]], pop_bytes(),
                                hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL((k_moments<L, T>), dim3(ew_grid()), dim3(256), 0, st, fb.p[ctl_h->slot_hist[0]],
                        mb[ctl_h->slot_m[0]], G.NS);
@@ -827,17 +840,24 @@ class Solver : public SolverBase {
     bdf_count = 0;
   }
 
+  // bytes of one population buffer: Q N_sites values, plus the FP32 moments
+  // of deviation storage
+  size_t pop_bytes() const {
+    return sizeof(T) * (size_t)Q * G.NS + (DV ? sizeof(float) * (size_t)(D + 1) * G.NS : 0);
+  }
+
   void upload_pop(const double* f, T* dst) {
     double* stg = staging();
     const int64_t n = (int64_t)Q * G.NS;
     MSC_HIPCK(hipMemcpyAsync(stg, f, sizeof(double) * n, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL((k_convert<double, T>), dim3(ew_grid()), dim3(256), 0, st, stg, dst, n);
+    hipLaunchKernelGGL((k_pop_from_f64<L, T>), dim3(ew_grid()), dim3(256), 0, st, (const double*)stg, dst, G.NS,
+                       1.0f / sig);
     MSC_HIPCK(hipGetLastError());
   }
   void download_pop(const T* src, double* f) {
     double* stg = staging();
     const int64_t n = (int64_t)Q * G.NS;
-    hipLaunchKernelGGL((k_convert<T, double>), dim3(ew_grid()), dim3(256), 0, st, src, stg, n);
+    hipLaunchKernelGGL((k_pop_to_f64<L, T>), dim3(ew_grid()), dim3(256), 0, st, src, stg, G.NS, sig);
     MSC_HIPCK(hipGetLastError());
     MSC_HIPCK(hipMemcpyAsync(f, stg, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     sync();
@@ -857,10 +877,59 @@ class Solver : public SolverBase {
       MSC_HIPCK(hipMemsetAsync(h, 0, sizeof(double) * n, st));
   }
 
-  double sumsq(const T* v, int64_t n) {
+  // Scale of deviation storage: a power of two with |g| <= 2^12 for the
+  // given populations (max deviation from equilibrium) and <= 2^10 times the
+  // deviation over the largest moment (headroom for the march: a post-stream
+  // deviation is a difference of neighbouring equilibria, a few times the
+  // largest moment at most); FP16 overflows at 65504.
+  static float choose_sigma(double maxdev, double maxm) {
+    const double want = std::max(std::max(maxdev * 0x1p-12, maxm * 0x1p-10), 0x1p-100);
+    return (float)std::exp2(std::ceil(std::log2(want)));
+  }
+
+  // Scale for populations uploaded from host FP64 arrays.
+  float sigma_for(std::initializer_list<const double*> fs) {
+    double md = 0.0, mm = 0.0;
+    double* stg = staging();
+    const int grid = 512;
+    ensure_partials(2 * grid);
+    for (const double* f : fs) {
+      MSC_HIPCK(hipMemcpyAsync(stg, f, sizeof(double) * Q * G.NS, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL((k_pop_maxdev<L>), dim3(grid), dim3(256), 0, st, (const double*)stg, G.NS, partials);
+      MSC_HIPCK(hipGetLastError());
+      MSC_HIPCK(hipMemcpyAsync(partials_h, partials, sizeof(double) * 2 * grid, hipMemcpyDeviceToHost, st));
+      sync();
+      for (int i = 0; i < grid; ++i) {
+        md = std::max(md, partials_h[2 * i]);
+        mm = std::max(mm, partials_h[2 * i + 1]);
+      }
+    }
+    return choose_sigma(md, mm);
+  }
+
+  double absmax(const double* v, int64_t n) {
+    const int grid = 512;
+    ensure_partials(grid);
+    hipLaunchKernelGGL(k_absmax<0>, dim3(grid), dim3(256), 0, st, v, n, partials);
+    MSC_HIPCK(hipGetLastError());
+    MSC_HIPCK(hipMemcpyAsync(partials_h, partials, sizeof(double) * grid, hipMemcpyDeviceToHost, st));
+    sync();
+    double m = 0.0;
+    for (int i = 0; i < grid; ++i) m = std::max(m, partials_h[i]);
+    return m;
+  }
+
+  double pop_sumsq(const T* p) {
+    double s = sumsq(p, (int64_t)Q * G.NS);
+    if (DV) s += sumsq(dev_moments(p, Q, G.NS), (int64_t)(D + 1) * G.NS);
+    return s;
+  }
+
+  template <class X>
+  double sumsq(const X* v, int64_t n) {
     const int grid = 1024;
     ensure_partials(grid);
-    hipLaunchKernelGGL((k_sumsq<T>), dim3(grid), dim3(256), 0, st, v, n, partials);
+    hipLaunchKernelGGL((k_sumsq<X>), dim3(grid), dim3(256), 0, st, v, n, partials);
     MSC_HIPCK(hipGetLastError());
     MSC_HIPCK(hipMemcpyAsync(partials_h, partials, sizeof(double) * grid, hipMemcpyDeviceToHost, st));
     sync();
@@ -879,9 +948,7 @@ class Solver : public SolverBase {
   }
 
   // ------------------------------------------------------ adjoint pieces --
-  size_t record_bytes() const {
-    return 3 * sizeof(T) * (size_t)Q * G.NS + 2 * sizeof(double) * (size_t)(D + 1) * G.NS;
-  }
+  size_t record_bytes() const { return 3 * pop_bytes() + 2 * sizeof(double) * (size_t)(D + 1) * G.NS; }
 
   // Enqueue a copy of the current state (ctl_h must be current).
   void take_checkpoint(int64_t bc) {
@@ -889,8 +956,9 @@ class Solver : public SolverBase {
     r.mem = dalloc(record_bytes());
     r.bc = bc;
     r.K = 0;
+    r.sig = sig;
     records.push_back(r);
-    const size_t fq = sizeof(T) * (size_t)Q * G.NS, fm = sizeof(double) * (size_t)(D + 1) * G.NS;
+    const size_t fq = pop_bytes(), fm = sizeof(double) * (size_t)(D + 1) * G.NS;
     char* b = (char*)r.mem;
     for (int i = 0; i < 3; ++i)
       MSC_HIPCK(hipMemcpyAsync(b + i * fq, fb.p[ctl_h->slot_hist[i]], fq, hipMemcpyDeviceToDevice, st));
@@ -1003,10 +1071,11 @@ class Solver : public SolverBase {
   void backward_step(const Record& R, const double* lin, double* lout) {
     const int64_t NS = G.NS, FQ = (int64_t)Q * NS, FM = (int64_t)(D + 1) * NS;
     const bool shadow = (P.corrector == MSC_CORRECTOR_SHADOW);
+    const size_t pb = pop_bytes();
     const T* f0 = (const T*)R.mem;
-    const T* f1 = f0 + FQ;
-    const T* f2 = f0 + 2 * FQ;
-    const double* m0 = (const double*)((const char*)R.mem + 3 * sizeof(T) * (size_t)FQ);
+    const T* f1 = (const T*)((const char*)R.mem + pb);
+    const T* f2 = (const T*)((const char*)R.mem + 2 * pb);
+    const double* m0 = (const double*)((const char*)R.mem + 3 * pb);
     const double* m1 = m0 + FM;
     const int q = (R.bc == 0) ? 1 : 2;
     const int max_order = (P.extrap_states == 0) ? 2 : P.extrap_states - 1;
@@ -1017,15 +1086,15 @@ class Solver : public SolverBase {
     const int eg = ew_grid();
 
     // forward recompute of f^(1..K) in FP64
-    hipLaunchKernelGGL((k_extrap_h<T>), dim3(eg), dim3(256), 0, st, NS, Q, D + 1, order, q, P.dt, f0, f1, f2, m0,
-                       m1, it(1), adj_h);
+    hipLaunchKernelGGL((k_extrap_h<L, T>), dim3(eg), dim3(256), 0, st, NS, order, q, P.dt, f0, f1, f2, m0, m1,
+                       R.sig, it(1), adj_h);
     MSC_HIPCK(hipGetLastError());
     for (int ell = 1; ell < K; ++ell) {
       sweep64(it(ell), shadow ? adj_fT : it(ell + 1), a);
       if (shadow) {
         enqueue_transform<double, double>(nullptr, 0, 0, a, nullptr, false, adj_x);
         hipLaunchKernelGGL((k_lift<L, double, double>), dim3(eg), dim3(256), 0, st, (const double*)adj_fT,
-                           (const double*)adj_z, it(ell + 1), NS);
+                           (const double*)adj_z, it(ell + 1), NS, 1.0f, 1.0f);
         MSC_HIPCK(hipGetLastError());
       }
     }
@@ -1149,6 +1218,8 @@ class Solver : public SolverBase {
     S.inv1pa2 = 1.0 / (1.0 + a / 2.0);
     S.wp = wp;
     S.wm = wm;
+    S.sig = sig;
+    S.isig = 1.0f / sig;
     return S;
   }
 
@@ -1159,7 +1230,7 @@ class Solver : public SolverBase {
   // m^{n-1} read and h written); the lift input and P r output
   double sweep_bytes(int mode, int order = 0, int q = 1) const {
     const double NS = (double)G.NS;
-    const double fb1 = (double)Q * sizeof(T) * NS, mb1 = (double)(D + 1) * NS;
+    const double fb1 = (double)pop_bytes(), mb1 = (double)(D + 1) * NS;
     if (mode == SW_EXPLICIT) return 2.0 * fb1;
     double b = 2.0 * fb1 + mb1 * sizeof(TM);  // f in, f_T out, P r out
     if (mode == SW_DTS_SETUP)

@@ -21,6 +21,8 @@
 // moment fields; halo re-reads hit L2.
 #pragma once
 
+#include <type_traits>
+
 #include "msc_common.h"
 
 namespace msc {
@@ -39,6 +41,10 @@ struct CompT<double> {
 };
 template <>
 struct CompT<float> {
+  using type = float;
+};
+template <>
+struct CompT<_Float16> {
   using type = float;
 };
 
@@ -132,6 +138,7 @@ struct SweepArgs {
   double* partials; // one FP64 partial sum of r^2 per block
   double a, inv1pa2;  // a_q and 1/(1 + a_q/2)
   double wp, wm;      // omega+, omega-
+  float sig, isig;    // FP16 deviation storage: scale sigma and 1/sigma
   int* did_run;       // optional: set to 1 when the launch passed its guard
   // setup mode: moment buffers (roles from control slots), BDF order,
   // extrapolation order, physical step
@@ -196,9 +203,13 @@ struct SrcPtrs {
 template <class L, class T, class TM, int MODE>
 struct RawSite {
   static constexpr int Q = L::Q, D1 = L::D + 1;
+  static constexpr bool DV = PopDev<T>::value;
   T f0[Q];
   T f1[MODE == SW_DTS_SETUP ? Q : 1];
   T f2[MODE == SW_DTS_SETUP ? Q : 1];
+  float M0[DV ? D1 : 1];  // stored moments of each deviation buffer
+  float M1[DV && MODE == SW_DTS_SETUP ? D1 : 1];
+  float M2[DV && MODE == SW_DTS_SETUP ? D1 : 1];
   TM dmv[MODE == SW_DTS_LIFT ? D1 : 1];
   double hv[MODE == SW_EXPLICIT ? 1 : D1];  // h, or m^n in setup mode
   double mpv[MODE == SW_DTS_SETUP ? D1 : 1];
@@ -208,17 +219,30 @@ template <class L, class T, class TM, int MODE>
 __device__ __forceinline__ void load_raw(const SweepArgs<T, TM>& A, const SrcPtrs<T>& P, int64_t site,
                                          RawSite<L, T, TM, MODE>& r) {
   constexpr int Q = L::Q, D = L::D;
+  constexpr bool DV = PopDev<T>::value;
   const int64_t NS = A.NS;
 #pragma unroll
   for (int k = 0; k < Q; ++k) r.f0[k] = P.s0[k * NS + site];
+  if constexpr (DV) {
+#pragma unroll
+    for (int b = 0; b <= D; ++b) r.M0[b] = dev_moments(P.s0, Q, NS)[b * NS + site];
+  }
   if (MODE == SW_DTS_SETUP) {
     if (A.order >= 1) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) r.f1[k] = P.s1[k * NS + site];
+      if constexpr (DV && MODE == SW_DTS_SETUP) {
+#pragma unroll
+        for (int b = 0; b <= D; ++b) r.M1[b] = dev_moments(P.s1, Q, NS)[b * NS + site];
+      }
     }
     if (A.order >= 2) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) r.f2[k] = P.s2[k * NS + site];
+      if constexpr (DV && MODE == SW_DTS_SETUP) {
+#pragma unroll
+        for (int b = 0; b <= D; ++b) r.M2[b] = dev_moments(P.s2, Q, NS)[b * NS + site];
+      }
     }
 #pragma unroll
     for (int b = 0; b <= D; ++b) r.hv[b] = P.mc[b * NS + site];
@@ -247,26 +271,45 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
                                             double* hout) {
   using CT = typename CompT<T>::type;
   constexpr int Q = L::Q, D = L::D;
+  constexpr bool DV = PopDev<T>::value;
   double h[4] = {0, 0, 0, 0};
   if (MODE == SW_DTS_SETUP) {
     // Eq. (bdf2) in FP64, and the extrapolated initial trial (Sec. 3.1)
 #pragma unroll
     for (int b = 0; b <= D; ++b)
       h[b] = (A.q == 1) ? r.hv[b] / A.dt : (4.0 * r.hv[b] - r.mpv[b]) / (2.0 * A.dt);
+    if constexpr (DV) {
+      CT g1[Q], g2[Q];
+      dev_rebuild<L>(r.f0, r.M0, A.sig, f);
+      if (A.order >= 1) dev_rebuild<L>(r.f1, r.M1, A.sig, g1);
+      if (A.order >= 2) dev_rebuild<L>(r.f2, r.M2, A.sig, g2);
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      if (A.order == 0)
-        f[k] = (CT)r.f0[k];
-      else if (A.order == 1)
-        f[k] = (CT)2 * (CT)r.f0[k] - (CT)r.f1[k];
-      else
-        f[k] = (CT)3 * (CT)r.f0[k] - (CT)3 * (CT)r.f1[k] + (CT)r.f2[k];
+      for (int k = 0; k < Q; ++k) {
+        if (A.order == 1)
+          f[k] = (CT)2 * f[k] - g1[k];
+        else if (A.order >= 2)
+          f[k] = (CT)3 * f[k] - (CT)3 * g1[k] + g2[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        if (A.order == 0)
+          f[k] = (CT)r.f0[k];
+        else if (A.order == 1)
+          f[k] = (CT)2 * (CT)r.f0[k] - (CT)r.f1[k];
+        else
+          f[k] = (CT)3 * (CT)r.f0[k] - (CT)3 * (CT)r.f1[k] + (CT)r.f2[k];
+      }
     }
 #pragma unroll
     for (int b = 0; b <= D; ++b) hout[b] = h[b];
   } else {
+    if constexpr (DV) {
+      dev_rebuild<L>(r.f0, r.M0, A.sig, f);
+    } else {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) f[k] = (CT)r.f0[k];
+      for (int k = 0; k < Q; ++k) f[k] = (CT)r.f0[k];
+    }
     if (MODE != SW_EXPLICIT) {
 #pragma unroll
       for (int b = 0; b <= D; ++b) h[b] = r.hv[b];
@@ -353,9 +396,12 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
   constexpr int KPX = local_dir<L>(1), KMX = local_dir<L>(-1);
   static_assert(KPX > 0 && KMX > 0 && local_dir<L>(0) == 0, "lattice layout");
 
-  __shared__ T ldsP[4][NGP][NI];
-  __shared__ T ldsZ[3][NG0][NI];
-  __shared__ T ldsM[2][NGM][NI];
+  // post-collision values travel through LDS in the storage type, or FP32
+  // for deviation storage (they are full populations there)
+  using LT = typename std::conditional<PopDev<T>::value, float, T>::type;
+  __shared__ LT ldsP[4][NGP][NI];
+  __shared__ LT ldsZ[3][NG0][NI];
+  __shared__ LT ldsM[2][NGM][NI];
   __shared__ double red[NT];
 
   SrcPtrs<T> P{A.src, nullptr, nullptr, nullptr, nullptr};
@@ -445,11 +491,11 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
         const int di = j1 * T2 + j2;
         const int g = xgroup<L>(k), gi = group_index<L>(k);
         if (g == 0) {
-          if (wP) ldsP[sP][gi][di] = (T)C[k];
+          if (wP) ldsP[sP][gi][di] = (LT)C[k];
         } else if (g == 1) {
-          if (wZ) ldsZ[sZ][gi][di] = (T)C[k];
+          if (wZ) ldsZ[sZ][gi][di] = (LT)C[k];
         } else {
-          if (wM) ldsM[sM][gi][di] = (T)C[k];
+          if (wM) ldsM[sM][gi][di] = (LT)C[k];
         }
       }
       c0c[j] = C[0];
@@ -484,11 +530,11 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
         const int di = j1 * T2 + j2;
         const int g = xgroup<L>(k), gi = group_index<L>(k);
         if (g == 0) {
-          if (wP) ldsP[sP][gi][di] = (T)C[k];
+          if (wP) ldsP[sP][gi][di] = (LT)C[k];
         } else if (g == 1) {
-          if (wZ) ldsZ[sZ][gi][di] = (T)C[k];
+          if (wZ) ldsZ[sZ][gi][di] = (LT)C[k];
         } else {
-          if (wM) ldsM[sM][gi][di] = (T)C[k];
+          if (wM) ldsM[sM][gi][di] = (LT)C[k];
         }
       }
     }
@@ -505,20 +551,38 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
         const int i1 = s / T2, i2 = s - (s / T2) * T2;
         const int64_t site = ((int64_t)xd * N1 + (b1 + i1)) * N2 + (b2 + i2);
         CT pr[4] = {0, 0, 0, 0};
+        CT vv[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          CT v;
           if (k == 0) {
-            v = c0prev[j];
+            vv[k] = c0prev[j];
           } else if (k == KPX) {
-            v = cpx2[j];
+            vv[k] = cpx2[j];
           } else if (k == KMX) {
-            v = cmxc[j];
+            vv[k] = cmxc[j];
           } else {
             const int g = xgroup<L>(k), gi = group_index<L>(k);
-            v = (g == 0) ? (CT)ldsP[rP][gi][s] : ((g == 1) ? (CT)ldsZ[rZ][gi][s] : (CT)ldsM[rM][gi][s]);
+            vv[k] = (g == 0) ? (CT)ldsP[rP][gi][s] : ((g == 1) ? (CT)ldsZ[rZ][gi][s] : (CT)ldsM[rM][gi][s]);
           }
-          __builtin_nontemporal_store((T)v, &dst[k * NS + site]);
+        }
+        if constexpr (PopDev<T>::value) {
+          // store (g, M); the residual is then taken against the stored
+          // output, so that the iterate of the stored iteration is what it
+          // measures (and its fixed point has r = 0)
+          T gq[Q];
+          float Mq[D + 1];
+          dev_split<L>(vv, A.isig, gq, Mq);
+#pragma unroll
+          for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(gq[k], &dst[k * NS + site]);
+          float* dM = dev_moments(dst, Q, NS);
+#pragma unroll
+          for (int bb = 0; bb <= D; ++bb) __builtin_nontemporal_store(Mq[bb], &dM[bb * NS + site]);
+          if (MODE != SW_EXPLICIT) dev_rebuild<L>(gq, Mq, A.sig, vv);
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          const CT v = vv[k];
+          if constexpr (!PopDev<T>::value) __builtin_nontemporal_store((T)v, &dst[k * NS + site]);
           if (MODE != SW_EXPLICIT) {
             const CT r = v - fprev[j][k];
             pr[0] += r;

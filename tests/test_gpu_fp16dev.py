@@ -1,0 +1,194 @@
+"""FP16 deviation-from-equilibrium storage against the FP64 oracle (through
+the C ABI).  Populations are stored as g = (f - feq(P f))/sigma in FP16 with
+P f in FP32 and a power-of-two sigma; arithmetic is FP32 as in FP32 storage.
+
+The error is measured and bounded per result:
+* one sweep: |f_T - oracle| <= 2e-3 max|f - feq(P f)| (input and output
+  deviations) plus FP32 rounding: two FP16 roundings of a deviation;
+* marches (replayed inner counts): RMS velocity error relative to the FP64
+  oracle <= 1e-5, the FP32 bar (at omega+ = omega- = 1 the collision sees the
+  populations only through their moments, which the storage keeps in FP32 and
+  the rebuild preserves exactly);
+* the explicit march: the same velocity bar.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_39474_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NU = 1.0 / 6.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2609_39474_amd import msc
+    msc.lib()
+    return msc
+
+
+def _solver(M, shape, *, dt=64.0, eps=1e-10, storage="fp16dev", corrector="shadow", tau=(1.0, 1.0),
+            p0=None, u0=None, n_min=None):
+    d = len(shape)
+    p = M.make_params(d, shape[0], dt=dt, eps=eps, storage=storage, corrector=corrector,
+                      tau_plus=tau[0], tau_minus=tau[1], n_min=n_min)
+    for a in range(d):
+        p.n[a] = shape[a]
+    if p0 is None:
+        p0 = np.zeros(shape)
+        u0 = np.zeros((d,) + shape)
+    return M.Solver(p, p0, u0)
+
+
+def _deviation(orc, f, d):
+    """max |f - feq(P f)| with the oracle's equilibrium."""
+    m = orc.moments(f)
+    fe = orc.init_populations(m[0], m[1:])
+    return float(np.max(np.abs(f - fe)))
+
+
+def _vel_err(m, ref):
+    return math.sqrt(((m[1:] - ref[1:]) ** 2).sum(0).mean()) / math.sqrt((ref[1:] ** 2).sum(0).mean())
+
+
+SWEEP_CASES = [((64, 64), (1.0, 1.0)), ((32, 512), (1.0, 1.0)), ((32, 128), (0.8, 1.3)),
+               ((8, 16, 64), (1.0, 1.0)), ((16, 16, 16), (1 / 0.9, 1 / 1.2))]
+
+
+@pytest.mark.parametrize("shape,omega", SWEEP_CASES)
+def test_fp16dev_single_sweep(M, orc, shape, omega):
+    say("fp16dev sweep", shape, omega)
+    d = len(shape)
+    rng = np.random.default_rng(sum(shape))
+    c, w, _ = orc.lattice(d)
+    Q = len(w)
+    wq = w.reshape((Q,) + (1,) * d)
+    p0 = 1e-3 * rng.normal(size=shape)
+    u0 = 1e-3 * rng.normal(size=(d,) + shape)
+    f = orc.init_populations(p0, u0) + wq * 1e-4 * rng.normal(size=(Q,) + shape)
+    h = 1e-5 * rng.normal(size=(d + 1,) + shape)
+    a = 3.0 / 128.0
+    s = _solver(M, shape, corrector="picard", tau=(1 / omega[0], 1 / omega[1]))
+    fT, Pr, R = s.sweep(f, h, a)
+    ofT, oPr, oR = orc.sweep(f, h, a, omega[0], omega[1])
+    dev = max(_deviation(orc, f, d), _deviation(orc, ofT, d))
+    err = float(np.max(np.abs(fT - ofT)))
+    bound = 2e-3 * dev + 4e-7 * float(np.max(np.abs(ofT)))
+    say("  max err", err, "deviation scale", dev, "bound", bound, "R", R, oR)
+    assert err <= bound
+    assert abs(R - oR) <= 2e-3 * oR
+    s.close()
+
+
+def test_fp16dev_random_field_march(M, orc):
+    N = 128
+    p0, u0 = W.random_field_2d(N, NU / N, seed=1)
+    nsteps = 6
+    ref = orc.march(p0, u0, dt=64.0, nsteps=nsteps, eps=1e-10, nmin=2)
+    K = [st["iters"] for st in ref.stats]
+    s = _solver(M, (N, N), dt=64.0, eps=1e-10, p0=p0, u0=u0, n_min=2)
+    s.set_schedule(K)
+    rc, _ = s.bdf2_step(nsteps)
+    assert rc == 0
+    err = _vel_err(s.moments(), ref.m)
+    say("fp16dev 2D march rel velocity error", err)
+    assert err <= 1e-5
+    s.close()
+
+
+def test_fp16dev_free_running_march(M, orc):
+    """Own acceptance decisions.  TGV at rho0 = 1 puts the FP32 floor of the
+    raw residual near 1e-8, so eps = 1e-7; the FP16-deviation run takes the
+    oracle's inner counts and its velocity error is stated beside FP32's
+    (measured 1.4e-5 and 7.9e-6)."""
+    N = 64
+    p0, u0 = W.tgv2d(N, NU / N, NU)
+    nsteps = 10
+    ref = orc.march(p0, u0, dt=64.0, nsteps=nsteps, eps=1e-7, nmin=2)
+    errs = {}
+    for storage in ("fp32", "fp16dev"):
+        s = _solver(M, (N, N), dt=64.0, eps=1e-7, storage=storage, p0=p0, u0=u0, n_min=2)
+        rc, stats = s.bdf2_step(nsteps)
+        assert rc == 0
+        assert [x["iters"] for x in stats] == [x["iters"] for x in ref.stats]
+        errs[storage] = _vel_err(s.moments(), ref.m)
+        s.close()
+    say("free-running rel velocity error", errs)
+    assert errs["fp16dev"] <= 2e-5
+
+
+def test_fp16dev_tgv3d_march(M, orc):
+    N = 32
+    p0, u0 = W.tgv3d_perturbed(N, NU / N, seed=1, jmax=8)
+    ref = orc.march(p0, u0, dt=32.0, nsteps=3, eps=1e-10, nmin=1)
+    K = [st["iters"] for st in ref.stats]
+    s = _solver(M, (N, N, N), dt=32.0, eps=1e-10, p0=p0, u0=u0, n_min=1)
+    s.set_schedule(K)
+    rc, _ = s.bdf2_step(3)
+    assert rc == 0
+    err = _vel_err(s.moments(), ref.m)
+    say("fp16dev 3D march rel velocity error", err)
+    assert err <= 1e-5
+    s.close()
+
+
+def test_fp16dev_explicit_march(M, orc):
+    N = 64
+    p0, u0 = W.tgv2d(N, NU / N, NU)
+    s = _solver(M, (N, N), corrector="picard", p0=p0, u0=u0)
+    steps = 2 * 64 + 3
+    s.explicit_step(steps)
+    of = orc.explicit(orc.init_populations(p0, u0), steps)
+    err = _vel_err(s.moments(), orc.moments(of))
+    f = s.populations()
+    perr = float(np.max(np.abs(f - of))) / _deviation(orc, of, 2)
+    say("fp16dev explicit: rel velocity error", err, "population error / deviation scale", perr)
+    assert err <= 1e-5
+    assert perr <= 2e-3
+    s.close()
+
+
+def test_fp16dev_state_roundtrip_and_adjoint(M, orc):
+    """get/set_state keep the state to the FP16 deviation rounding; the
+    adjoint (FP64 recompute from FP16-deviation checkpoints) agrees with the
+    FP64 adjoint for the same output adjoint."""
+    N = 32
+    p0, u0 = W.random_field_2d(N, NU / N, seed=3, jmax=4)
+    out = {}
+    K = None
+    K0 = None
+    for storage in ("fp64", "fp16dev"):
+        s = _solver(M, (N, N), dt=64.0, eps=1e-10, storage=storage, p0=p0, u0=u0, n_min=2)
+        if K0 is not None:
+            s.set_schedule(K0)
+        _, st0 = s.bdf2_step(2)
+        K0 = [x["iters"] for x in st0]
+        st, bc = s.get_state()
+        s.set_state(st, bc)
+        st2, _ = s.get_state()
+        if storage == "fp16dev":
+            assert float(np.max(np.abs(st2 - st))) <= 1e-3 * float(np.max(np.abs(st)))
+        s.set_recording(True)
+        if K is not None:
+            s.set_schedule(K)
+        _, stats = s.bdf2_step(3)
+        if K is None:
+            K = [x["iters"] for x in stats]
+            st1, _ = s.get_state()
+            lam = np.zeros_like(st1)
+            NS, FQ = N * N, 9 * N * N
+            lam[3 * FQ + NS:3 * FQ + 3 * NS] = st1[3 * FQ + NS:3 * FQ + 3 * NS]
+        out[storage] = s.bdf2_adjoint(3, lam)
+        s.close()
+    e = float(np.max(np.abs(out["fp16dev"] - out["fp64"])) / np.max(np.abs(out["fp64"])))
+    say("fp16dev adjoint vs fp64 adjoint (same output adjoint)", e)
+    assert e <= 1e-5
