@@ -1175,9 +1175,9 @@ class Solver : public SolverBase {
         if (t.T1 > G.N1 || t.T2 > G.N2) continue;
         if (wide_fits && t.NT < 64) continue;
         if (D == 3 && t.T1 == 16 && G.N2 >= 32 && G.N1 >= 8) continue;  // 8 x 32 coalesces better
-        const int64_t tiles = (int64_t)(G.N1 / t.T1) * (G.N2 / t.T2);
-        // largest tile that still leaves >= 256 blocks at 4 planes per strip
-        if (best < 0 || tiles * std::max(1, G.N0 / 4) >= 256) best = i;
+        // the largest tile that fits (measured best at every size; the strip
+        // length below supplies the parallelism)
+        best = i;
       }
     }
     tile_id = best;
@@ -1185,9 +1185,14 @@ class Solver : public SolverBase {
     const int64_t tiles = (int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2);
     int Lp = tune.sweep_strip;
     if (Lp <= 0) {
-      int64_t want = (tiles * G.N0) / 512;
+      // Longest strip that keeps >= 1024 blocks (2D) or >= 512 (3D, more
+      // work per site): short strips cut the per-block chain of plane steps,
+      // which bounds small grids; long ones cut the two halo planes per
+      // strip.  Measured optimum of the sweep at N = 256 ... 4096 (2D) and
+      // N = 64, 128 (3D).
+      const int64_t target = (D == 2) ? 1024 : 512;
       Lp = 1;
-      while (Lp * 2 <= want && Lp < 64) Lp *= 2;
+      while (Lp < 64 && tiles * (G.N0 / (Lp * 2)) >= target) Lp *= 2;
     }
     Lp = std::min(Lp, G.N0);
     while (G.N0 % Lp) Lp >>= 1;
