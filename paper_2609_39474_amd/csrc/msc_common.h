@@ -96,13 +96,21 @@ struct StepStat {
   int32_t converged, fail;
 };
 
-struct DevCtl {
-  uint64_t phase;
-  int32_t fail_code;
+// Buffer roles during one physical step.
+struct Roles {
   int32_t slot_hist[3];  // population buffer index of f^n, f^{n-1}, f^{n-2}
   int32_t slot_w[2];     // the two working buffers of the inner iteration
   int32_t slot_m[3];     // moment buffer index of m^n, m^{n-1} and the spare
+};
+
+// The roles of step n live in roles[n & 1]: the acceptance of step n writes
+// the rotated roles of step n + 1 into the other copy, so the kernel that
+// decides the acceptance can still read step n's roles in every block.
+struct DevCtl {
+  uint64_t phase;
+  int32_t fail_code;
   int32_t pad;
+  Roles roles[2];
 };
 
 // Population buffers (five, roles assigned through DevCtl slots).

@@ -180,7 +180,7 @@ struct CorrGuard {
 template <class CT, class TM>
 struct Fft2Args {
   CorrGuard g;
-  int do_accept;  // first pass also reconstructs m^{n+1} when step n accepted at ell
+  int do_accept;  // Algorithm 1 mode: the first pass decides acceptance (and reconstructs m^{n+1})
   int adjoint;    // apply chi H^{-H} (transpose of the correction) instead of chi H^{-1}
   int Nx, Ny, lgx, lgy;
   int NBy;      // N_y/4 + 1
@@ -194,14 +194,22 @@ struct Fft2Args {
 };
 
 template <class L, class T, class CT, class TM>
-__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A, AcceptArgs<L, T> Ac) {
-  if (A.do_accept && A.g.ctl && phase_accepted(A.g.ctl->phase, A.g.n, A.g.ell)) {
-    // accepted at this sweep: reconstruct m^{n+1} on this block's rows instead
-    const int64_t s0 = (int64_t)blockIdx.x * A.rows_per_block * A.Ny;
-    accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)A.rows_per_block * A.Ny, blockDim.x);
+__global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A, AcceptArgs<L, T> Ac, FinishArgs Fin) {
+  if (A.do_accept) {
+    // Algorithm 1: decide on sweep ell of step n here; if accepted,
+    // reconstruct m^{n+1} on this block's rows instead of transforming
+    __shared__ double red[256];
+    const int dec = finish_block(Fin, red);
+    if (dec != DEC_RUNNING) {
+      if (dec == DEC_ACCEPTED) {
+        const int64_t s0 = (int64_t)blockIdx.x * A.rows_per_block * A.Ny;
+        accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)A.rows_per_block * A.Ny, blockDim.x);
+      }
+      return;
+    }
+  } else if (A.g.skip()) {
     return;
   }
-  if (A.g.skip()) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
   const int Ny = A.Ny, R = A.rows_per_block;
@@ -370,14 +378,21 @@ __device__ inline int band_to_j(int i, int N, int NB) { return (i <= N / 4) ? i 
 
 // pass 1: forward along z of pencils (x, y); fields (0,1) and (2,3) packed
 template <class L, class T, class CT, class TM>
-__global__ __launch_bounds__(256) void k_fft3_z_fwd(Fft3Args<CT, TM> A, AcceptArgs<L, T> Ac) {
+__global__ __launch_bounds__(256) void k_fft3_z_fwd(Fft3Args<CT, TM> A, AcceptArgs<L, T> Ac, FinishArgs Fin) {
   const int R = A.pencils_per_block, Nz = A.Nz;
-  if (A.do_accept && A.g.ctl && phase_accepted(A.g.ctl->phase, A.g.n, A.g.ell)) {
-    const int64_t s0 = (int64_t)blockIdx.x * R * Nz;
-    accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)R * Nz, blockDim.x);
+  if (A.do_accept) {
+    __shared__ double red[256];
+    const int dec = finish_block(Fin, red);
+    if (dec != DEC_RUNNING) {
+      if (dec == DEC_ACCEPTED) {
+        const int64_t s0 = (int64_t)blockIdx.x * R * Nz;
+        accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)R * Nz, blockDim.x);
+      }
+      return;
+    }
+  } else if (A.g.skip()) {
     return;
   }
-  if (A.g.skip()) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
   cpx<CT>* tmp = buf + 2 * R * Nz;

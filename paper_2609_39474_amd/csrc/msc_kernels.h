@@ -76,10 +76,14 @@ __device__ inline void site_store(T* f, int64_t NS, int64_t s, float isig, const
   }
 }
 
+// The accepted populations are step n's working buffer of sweep ell; m^{n+1}
+// goes to step n's spare moment slot (the roles of step n + 1 name them f^n
+// and m^n).
 template <class L, class T>
 __device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64_t s1, int64_t stride) {
-  const T* f = A.fb.p[A.ctl->slot_hist[0]];
-  double* m = A.mb[A.ctl->slot_m[0]];
+  const Roles& ro = A.ctl->roles[A.n & 1];
+  const T* f = A.fb.p[ro.slot_w[A.ell & 1]];
+  double* m = A.mb[ro.slot_m[2]];
   const int64_t NS = A.NS;
   for (int64_t s = s0; s < s1; s += stride) {
     double M[4];
@@ -89,9 +93,12 @@ __device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64
   }
 }
 
+// Without the shadow corrector: the acceptance decision and, if accepted,
+// the reconstruction.
 template <class L, class T>
-__global__ void k_accept(AcceptArgs<L, T> A) {
-  if (!phase_accepted(A.ctl->phase, A.n, A.ell)) return;
+__global__ __launch_bounds__(256) void k_accept(AcceptArgs<L, T> A, FinishArgs F) {
+  __shared__ double red[256];
+  if (finish_block(F, red) != DEC_ACCEPTED) return;
   accept_sites<L, T>(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, A.NS, (int64_t)gridDim.x * blockDim.x);
 }
 

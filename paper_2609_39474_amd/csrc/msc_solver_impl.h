@@ -157,10 +157,14 @@ class Solver : public SolverBase {
       // control block: slots 0,1,2 hold f^n, f^{n-1}, f^{n-2}; 3,4 work.
       std::memset(ctl_h, 0, sizeof(DevCtl));
       ctl_h->phase = make_phase(-1, 0, PH_ACCEPTED);
-      for (int i = 0; i < 3; ++i) ctl_h->slot_hist[i] = i;
-      ctl_h->slot_w[0] = 3;
-      ctl_h->slot_w[1] = 4;
-      for (int i = 0; i < 3; ++i) ctl_h->slot_m[i] = i;
+      for (int r = 0; r < 2; ++r) {
+        Roles& ro = ctl_h->roles[r];
+        for (int i = 0; i < 3; ++i) ro.slot_hist[i] = i;
+        ro.slot_w[0] = 3;
+        ro.slot_w[1] = 4;
+        for (int i = 0; i < 3; ++i) ro.slot_m[i] = i;
+      }
+      n_next = 0;
       MSC_HIPCK(hipMemcpyAsync(ctl, ctl_h, sizeof(DevCtl), hipMemcpyHostToDevice, st));
       if (DV) sig = choose_sigma(0.0, std::max(absmax(pd, NS), absmax(ud, (int64_t)D * NS)));
       hipLaunchKernelGGL((k_init_feq<L, T>), dim3(ew_grid()), dim3(256), 0, st, pd, ud, fb.p[0], NS);
@@ -200,7 +204,7 @@ class Solver : public SolverBase {
         // while recording, one step per synchronisation so that the state at
         // each step's start can be checkpointed
         const int B = recording ? 1 : std::min(batch, n_end - n_dev);
-        if (recording && ell_dev == 1) take_checkpoint(bdf_dev);
+        if (recording && ell_dev == 1) take_checkpoint(n_dev, bdf_dev);
         for (int i = 0; i < B; ++i) {
           const int n = n_dev + i;
           const int64_t bc = bdf_dev + i;
@@ -269,8 +273,8 @@ class Solver : public SolverBase {
   msc_status explicit_step(int64_t nsteps) override {
     return guard([&]() -> msc_status {
       pull_ctl();
-      T* A = fb.p[ctl_h->slot_hist[0]];
-      T* B = fb.p[ctl_h->slot_w[0]];
+      T* A = fb.p[cur_roles().slot_hist[0]];
+      T* B = fb.p[cur_roles().slot_w[0]];
       SweepArgs<T, TM> S = sweep_args(0.0);
       const int64_t chunk = 64;
       int64_t done = 0;
@@ -283,11 +287,11 @@ class Solver : public SolverBase {
         S.dst = (done & 1) ? A : B;
         launch_sweep_timed(SW_EXPLICIT, S, 1);
       }
-      if (nsteps & 1) std::swap(ctl_h->slot_hist[0], ctl_h->slot_w[0]);
+      if (nsteps & 1) std::swap(cur_roles().slot_hist[0], cur_roles().slot_w[0]);
       MSC_HIPCK(hipMemcpyAsync(ctl, ctl_h, sizeof(DevCtl), hipMemcpyHostToDevice, st));
       reset_history_from_current();
       // non-finite check on the final state
-      const double ss = pop_sumsq(fb.p[ctl_h->slot_hist[0]]);
+      const double ss = pop_sumsq(fb.p[cur_roles().slot_hist[0]]);
       if (!std::isfinite(ss)) {
         last_error = "non-finite population after the explicit march";
         return MSC_ERR_NONFINITE;
@@ -300,7 +304,7 @@ class Solver : public SolverBase {
   msc_status moments(double* phat, double* u, bool on_device) override {
     return guard([&]() {
       pull_ctl();
-      const double* m = mb[ctl_h->slot_m[0]];
+      const double* m = mb[cur_roles().slot_m[0]];
       const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
       if (phat) MSC_HIPCK(hipMemcpyAsync(phat, m, sizeof(double) * G.NS, kind, st));
       if (u) MSC_HIPCK(hipMemcpyAsync(u, m + G.NS, sizeof(double) * D * G.NS, kind, st));
@@ -332,7 +336,7 @@ class Solver : public SolverBase {
   msc_status get_populations(double* f) override {
     return guard([&]() {
       pull_ctl();
-      download_pop(fb.p[ctl_h->slot_hist[0]], f);
+      download_pop(fb.p[cur_roles().slot_hist[0]], f);
       return MSC_OK;
     });
   }
@@ -341,7 +345,7 @@ class Solver : public SolverBase {
     return guard([&]() {
       pull_ctl();
       if (DV) sig = sigma_for({f});
-      upload_pop(f, fb.p[ctl_h->slot_hist[0]]);
+      upload_pop(f, fb.p[cur_roles().slot_hist[0]]);
       reset_history_from_current();
       sync();
       return MSC_OK;
@@ -353,8 +357,8 @@ class Solver : public SolverBase {
                    double* R) override {
     return guard([&]() {
       pull_ctl();
-      T* A = fb.p[ctl_h->slot_w[0]];
-      T* B = fb.p[ctl_h->slot_w[1]];
+      T* A = fb.p[cur_roles().slot_w[0]];
+      T* B = fb.p[cur_roles().slot_w[1]];
       const float sig_state = sig;  // the work buffers may take another scale
       if (DV) sig = sigma_for({f});
       upload_pop(f, A);
@@ -381,8 +385,8 @@ class Solver : public SolverBase {
         return MSC_ERR_UNSUPPORTED;
       }
       pull_ctl();
-      T* A = fb.p[ctl_h->slot_w[0]];
-      T* B = fb.p[ctl_h->slot_w[1]];
+      T* A = fb.p[cur_roles().slot_w[0]];
+      T* B = fb.p[cur_roles().slot_w[1]];
       const float sig_state = sig;
       if (DV) sig = sigma_for({f});
       upload_pop(f, A);
@@ -431,10 +435,10 @@ class Solver : public SolverBase {
     return guard([&]() {
       pull_ctl();
       const int64_t FQ = (int64_t)Q * G.NS, FM = (int64_t)(D + 1) * G.NS;
-      for (int i = 0; i < 3; ++i) download_pop(fb.p[ctl_h->slot_hist[i]], state + i * FQ);
-      MSC_HIPCK(hipMemcpyAsync(state + 3 * FQ, mb[ctl_h->slot_m[0]], sizeof(double) * FM,
+      for (int i = 0; i < 3; ++i) download_pop(fb.p[cur_roles().slot_hist[i]], state + i * FQ);
+      MSC_HIPCK(hipMemcpyAsync(state + 3 * FQ, mb[cur_roles().slot_m[0]], sizeof(double) * FM,
                                hipMemcpyDeviceToHost, st));
-      MSC_HIPCK(hipMemcpyAsync(state + 3 * FQ + FM, mb[ctl_h->slot_m[1]], sizeof(double) * FM,
+      MSC_HIPCK(hipMemcpyAsync(state + 3 * FQ + FM, mb[cur_roles().slot_m[1]], sizeof(double) * FM,
                                hipMemcpyDeviceToHost, st));
       sync();
       if (bc) *bc = bdf_count;
@@ -447,10 +451,10 @@ class Solver : public SolverBase {
       pull_ctl();
       const int64_t FQ = (int64_t)Q * G.NS, FM = (int64_t)(D + 1) * G.NS;
       if (DV) sig = sigma_for({state, state + FQ, state + 2 * FQ});
-      for (int i = 0; i < 3; ++i) upload_pop(state + i * FQ, fb.p[ctl_h->slot_hist[i]]);
-      MSC_HIPCK(hipMemcpyAsync(mb[ctl_h->slot_m[0]], state + 3 * FQ, sizeof(double) * FM,
+      for (int i = 0; i < 3; ++i) upload_pop(state + i * FQ, fb.p[cur_roles().slot_hist[i]]);
+      MSC_HIPCK(hipMemcpyAsync(mb[cur_roles().slot_m[0]], state + 3 * FQ, sizeof(double) * FM,
                                hipMemcpyHostToDevice, st));
-      MSC_HIPCK(hipMemcpyAsync(mb[ctl_h->slot_m[1]], state + 3 * FQ + FM, sizeof(double) * FM,
+      MSC_HIPCK(hipMemcpyAsync(mb[cur_roles().slot_m[1]], state + 3 * FQ + FM, sizeof(double) * FM,
                                hipMemcpyHostToDevice, st));
       sync();
       bdf_count = bc;
@@ -575,6 +579,8 @@ class Solver : public SolverBase {
   cpx<CT>* spec2 = nullptr;
   double* partials = nullptr;
   double* partials_h = nullptr;
+  double* presum = nullptr;                   // folded partials for large sweep grids
+  static constexpr int kFusedParts = 4096;    // decision kernels sum at most this many partials
   int nparts_cap = 0;
   DevCtl* ctl = nullptr;
   DevCtl* ctl_h = nullptr;
@@ -716,6 +722,7 @@ class Solver : public SolverBase {
     ctl = keep((DevCtl*)dalloc(sizeof(DevCtl)));
     MSC_HIPCK(hipHostMalloc((void**)&ctl_h, sizeof(DevCtl), hipHostMallocDefault));
     Rhist = keep((double*)dalloc(sizeof(double) * std::max(P.k_max, 1)));
+    presum = keep((double*)dalloc(sizeof(double)));
     choose_sweep();
     ensure_partials(sweep_grid());
     if (corrector_supported()) {
@@ -821,6 +828,9 @@ class Solver : public SolverBase {
     }
   }
 
+  // Buffer roles of the next step to run (host copy; pull_ctl first).
+  Roles& cur_roles() { return ctl_h->roles[n_next & 1]; }
+
   void pull_ctl() {
     MSC_HIPCK(hipMemcpyAsync(ctl_h, ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
     sync();
@@ -830,12 +840,12 @@ class Solver : public SolverBase {
   // (next step BDF1, whose trial uses f^n alone).
   void reset_history_from_current() {
     for (int i = 1; i < 3; ++i)
-      MSC_HIPCK(hipMemcpyAsync(fb.p[ctl_h->slot_hist[i]], fb.p[ctl_h->slot_hist[0]], pop_bytes(),
+      MSC_HIPCK(hipMemcpyAsync(fb.p[cur_roles().slot_hist[i]], fb.p[cur_roles().slot_hist[0]], pop_bytes(),
                                hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL((k_moments<L, T>), dim3(ew_grid()), dim3(256), 0, st, fb.p[ctl_h->slot_hist[0]],
-                       mb[ctl_h->slot_m[0]], G.NS);
+    hipLaunchKernelGGL((k_moments<L, T>), dim3(ew_grid()), dim3(256), 0, st, fb.p[cur_roles().slot_hist[0]],
+                       mb[cur_roles().slot_m[0]], G.NS);
     MSC_HIPCK(hipGetLastError());
-    MSC_HIPCK(hipMemcpyAsync(mb[ctl_h->slot_m[1]], mb[ctl_h->slot_m[0]], sizeof(double) * (D + 1) * G.NS,
+    MSC_HIPCK(hipMemcpyAsync(mb[cur_roles().slot_m[1]], mb[cur_roles().slot_m[0]], sizeof(double) * (D + 1) * G.NS,
                              hipMemcpyDeviceToDevice, st));
     bdf_count = 0;
   }
@@ -950,8 +960,9 @@ class Solver : public SolverBase {
   // ------------------------------------------------------ adjoint pieces --
   size_t record_bytes() const { return 3 * pop_bytes() + 2 * sizeof(double) * (size_t)(D + 1) * G.NS; }
 
-  // Enqueue a copy of the current state (ctl_h must be current).
-  void take_checkpoint(int64_t bc) {
+  // Enqueue a copy of the state at the start of step n (ctl_h must be current).
+  void take_checkpoint(int n, int64_t bc) {
+    const Roles& ro = ctl_h->roles[n & 1];
     Record r{};
     r.mem = dalloc(record_bytes());
     r.bc = bc;
@@ -961,9 +972,9 @@ class Solver : public SolverBase {
     const size_t fq = pop_bytes(), fm = sizeof(double) * (size_t)(D + 1) * G.NS;
     char* b = (char*)r.mem;
     for (int i = 0; i < 3; ++i)
-      MSC_HIPCK(hipMemcpyAsync(b + i * fq, fb.p[ctl_h->slot_hist[i]], fq, hipMemcpyDeviceToDevice, st));
+      MSC_HIPCK(hipMemcpyAsync(b + i * fq, fb.p[ro.slot_hist[i]], fq, hipMemcpyDeviceToDevice, st));
     for (int i = 0; i < 2; ++i)
-      MSC_HIPCK(hipMemcpyAsync(b + 3 * fq + i * fm, mb[ctl_h->slot_m[i]], fm, hipMemcpyDeviceToDevice, st));
+      MSC_HIPCK(hipMemcpyAsync(b + 3 * fq + i * fm, mb[ro.slot_m[i]], fm, hipMemcpyDeviceToDevice, st));
   }
 
   void drop_last_record() {
@@ -1359,20 +1370,28 @@ class Solver : public SolverBase {
     F.Rhist = Rhist;
     F.stats = stats_d;
     F.stat_base = stat_base;
+    F.partials = partials;
+    F.nparts = sweep_grid();
     int mode;
     if (ell == 1)
       mode = SW_DTS_SETUP;
     else
       mode = (P.corrector == MSC_CORRECTOR_SHADOW) ? SW_DTS_LIFT : SW_DTS;
     launch_sweep_timed(mode, S, 0);
-    hipLaunchKernelGGL(k_finish<0>, dim3(1), dim3(256), 0, st, F, (const double*)partials, sweep_grid());
-    MSC_HIPCK(hipGetLastError());
+    if (F.nparts > kFusedParts) {
+      // many sweep blocks: fold the partials once instead of in every block
+      hipLaunchKernelGGL(k_presum<0>, dim3(1), dim3(256), 0, st, (const double*)partials, F.nparts, presum);
+      MSC_HIPCK(hipGetLastError());
+      F.partials = presum;
+      F.nparts = 1;
+    }
 
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
     if (P.corrector == MSC_CORRECTOR_SHADOW) {
-      enqueue_correction(ctl, n, ell, a, &Ac);
+      XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
+      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F);
     } else {
-      hipLaunchKernelGGL((k_accept<L, T>), dim3(ew_grid()), dim3(256), 0, st, Ac);
+      hipLaunchKernelGGL((k_accept<L, T>), dim3(ew_grid()), dim3(256), 0, st, Ac, F);
       MSC_HIPCK(hipGetLastError());
     }
   }
@@ -1466,8 +1485,9 @@ class Solver : public SolverBase {
 
   template <class CX, class TX>
   void enqueue_transform(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac, bool adjoint,
-                         const XformBufs<CX, TX>& B) {
+                         const XformBufs<CX, TX>& B, const FinishArgs* Fin = nullptr) {
     AcceptArgs<L, T> none{};
+    const FinishArgs nofin{};
     const size_t cb = sizeof(cpx<CX>);
     if constexpr (D == 2) {
       Fft2Args<CX, TX> F{};
@@ -1493,7 +1513,8 @@ class Solver : public SolverBase {
       const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
       const int grows = G.N0 / F.rows_per_block;
       const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
-      hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CX, TX>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none);
+      hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CX, TX>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none,
+                         Fin ? *Fin : nofin);
       MSC_HIPCK(hipGetLastError());
       hipLaunchKernelGGL((k_fft2_cols_solve<CX, TX>), dim3(gcols), dim3(256), cols_b, st, F);
       MSC_HIPCK(hipGetLastError());
@@ -1530,7 +1551,8 @@ class Solver : public SolverBase {
       const size_t xb = 8 * (size_t)JB * F.Nx * cb;
       const int ng = (F.NBz + JB - 1) / JB;
       const int gz = (int)(((int64_t)F.Nx * F.Ny) / R);
-      hipLaunchKernelGGL((k_fft3_z_fwd<L, T, CX, TX>), dim3(gz), dim3(256), zb, st, F, Ac ? *Ac : none);
+      hipLaunchKernelGGL((k_fft3_z_fwd<L, T, CX, TX>), dim3(gz), dim3(256), zb, st, F, Ac ? *Ac : none,
+                         Fin ? *Fin : nofin);
       MSC_HIPCK(hipGetLastError());
       hipLaunchKernelGGL((k_fft3_y_fwd<CX, TX>), dim3(F.Nx * ng), dim3(256), yb, st, F);
       MSC_HIPCK(hipGetLastError());

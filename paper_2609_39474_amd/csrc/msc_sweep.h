@@ -48,8 +48,11 @@ struct CompT<_Float16> {
   using type = float;
 };
 
-// Acceptance test of Algorithm 1, run by one thread once the global sum of
-// r^2 is known.
+// Acceptance test of Algorithm 1.  It runs at the start of the kernel that
+// follows the sweep (the first transform pass, or the reconstruction kernel
+// without the shadow corrector): every block sums the sweep's per-block
+// partials of r^2 in the same fixed order, so every block reaches the same
+// decision without waiting for another; block 0 alone records it.
 struct FinishArgs {
   DevCtl* ctl;
   int n, ell;
@@ -60,21 +63,20 @@ struct FinishArgs {
   double* Rhist;         // residual history of the current step
   StepStat* stats;       // stats[n - stat_base]
   int stat_base;
+  const double* partials;  // the sweep's per-block sums of r^2
+  int nparts;
 };
+
+enum { DEC_SKIP = -1, DEC_RUNNING = 0, DEC_ACCEPTED = 1, DEC_FAILED = 2 };
 
 // Raw residual RMS (Eq. residual) and the acceptance decision: accept when
 // ell >= n_min and the residual is finite and below eps (or at the scheduled
 // count in replay mode); a non-finite residual fails the step (Sec. 4.1);
-// reaching K_max fails it as nonconvergent.  On acceptance the population and
-// moment history slots rotate (Sec. 3.1, last paragraph); the moment slot
-// that becomes m^{n+1} is filled by the reconstruction kernel that follows.
-__device__ inline void finish_accept(const FinishArgs& A, double sum_r2) {
-  const double R = sqrt(sum_r2 * A.inv_count);
+// reaching K_max fails it as nonconvergent.
+__device__ inline int accept_decision(const FinishArgs& A, double R, int* fail_out) {
   const int ell = A.ell;
-  A.Rhist[ell - 1] = R;
   const bool fin = isfinite(R);
   const bool pass = A.sched ? (ell == A.sched[A.n - A.stat_base]) : (ell >= A.nmin && fin && R < A.eps);
-  DevCtl* c = A.ctl;
   int fail = 0;
   if (!pass) {
     if (!fin)
@@ -82,7 +84,20 @@ __device__ inline void finish_accept(const FinishArgs& A, double sum_r2) {
     else if (ell >= A.kmax)
       fail = 5;  // MSC_ERR_NONCONVERGED
   }
-  if (pass || fail) {
+  *fail_out = fail;
+  return pass ? DEC_ACCEPTED : (fail ? DEC_FAILED : DEC_RUNNING);
+}
+
+// Block 0's record of the decision: residual history, statistics (Eq.
+// rho-observed), on acceptance the rotated roles of step n + 1 (Sec. 3.1,
+// last paragraph: the histories shift; the moment slot that becomes m^{n+1}
+// is the spare, filled by the reconstruction of the same kernel), and the
+// phase word.
+__device__ inline void finish_commit(const FinishArgs& A, double R, int dec, int fail) {
+  const int ell = A.ell;
+  A.Rhist[ell - 1] = R;
+  DevCtl* c = A.ctl;
+  if (dec != DEC_RUNNING) {
     StepStat& st = A.stats[A.n - A.stat_base];
     st.q = A.q;
     st.iters = ell;
@@ -90,34 +105,61 @@ __device__ inline void finish_accept(const FinishArgs& A, double sum_r2) {
     st.R_final = R;
     double rho = __builtin_nan("");
     if (ell >= 3) {
-      // Eq. (rho-observed): tail geometric mean over m_rho = min(mcap, ell-1)
+      // tail geometric mean over m_rho = min(mcap, ell-1)
       const int mr = (A.mcap < ell - 1) ? A.mcap : ell - 1;
       double sl = 0.0;
       for (int j = ell - mr + 1; j <= ell; ++j) sl += log(A.Rhist[j - 1] / A.Rhist[j - 2]);
       rho = exp(sl / mr);
     }
     st.rho_obs = rho;
-    st.converged = pass ? 1 : 0;
+    st.converged = (dec == DEC_ACCEPTED) ? 1 : 0;
     st.fail = fail;
   }
-  if (pass) {
-    const int accb = c->slot_w[ell & 1];
-    const int old2 = c->slot_hist[2];
-    c->slot_hist[2] = c->slot_hist[1];
-    c->slot_hist[1] = c->slot_hist[0];
-    c->slot_hist[0] = accb;
-    c->slot_w[ell & 1] = old2;
-    const int mc = c->slot_m[0], mp = c->slot_m[1], ms = c->slot_m[2];
-    c->slot_m[0] = ms;  // becomes m^{n+1}
-    c->slot_m[1] = mc;
-    c->slot_m[2] = mp;
+  if (dec == DEC_ACCEPTED) {
+    const Roles& o = c->roles[A.n & 1];
+    Roles& r = c->roles[(A.n + 1) & 1];
+    r.slot_hist[0] = o.slot_w[ell & 1];
+    r.slot_hist[1] = o.slot_hist[0];
+    r.slot_hist[2] = o.slot_hist[1];
+    r.slot_w[ell & 1] = o.slot_hist[2];
+    r.slot_w[(ell + 1) & 1] = o.slot_w[(ell + 1) & 1];
+    r.slot_m[0] = o.slot_m[2];  // becomes m^{n+1}
+    r.slot_m[1] = o.slot_m[0];
+    r.slot_m[2] = o.slot_m[1];
     c->phase = make_phase(A.n, ell, PH_ACCEPTED);
-  } else if (fail) {
+  } else if (dec == DEC_FAILED) {
     c->fail_code = fail;
     c->phase = make_phase(A.n, ell, PH_FAILED);
   } else {
     c->phase = make_phase(A.n, ell, PH_RUNNING);
   }
+}
+
+// Block-uniform decision for (step n, sweep ell), or DEC_SKIP when the march
+// is not right after that sweep.  The phase word is either still the one the
+// sweep saw or already block 0's record of this very decision.  Uses red[256].
+__device__ inline int finish_block(const FinishArgs& A, double* red) {
+  __shared__ int sh_mine;
+  if (threadIdx.x == 0) {
+    const uint64_t ph = A.ctl->phase;
+    const bool after = phase_n(ph) == A.n && phase_ell(ph) == A.ell && phase_state(ph) != 0;
+    sh_mine = (phase_ready(ph, A.n, A.ell) || after) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!sh_mine) return DEC_SKIP;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < A.nparts; i += blockDim.x) acc += A.partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double R = sqrt(red[0] * A.inv_count);
+  int fail = 0;
+  const int dec = accept_decision(A, R, &fail);
+  if (blockIdx.x == 0 && threadIdx.x == 0) finish_commit(A, R, dec, fail);
+  return dec;
 }
 
 template <class T, class TM>
@@ -409,16 +451,17 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
   if (A.ctl) {
     const uint64_t ph = A.ctl->phase;
     if (!phase_ready(ph, A.n, A.ell)) return;  // uniform for the grid
+    const Roles& ro = A.ctl->roles[A.n & 1];
     if (MODE == SW_DTS_SETUP) {
-      P.s0 = A.fb.p[A.ctl->slot_hist[0]];
-      P.s1 = A.fb.p[A.ctl->slot_hist[1]];
-      P.s2 = A.fb.p[A.ctl->slot_hist[2]];
-      P.mc = A.mb[A.ctl->slot_m[0]];
-      P.mp = A.mb[A.ctl->slot_m[1]];
+      P.s0 = A.fb.p[ro.slot_hist[0]];
+      P.s1 = A.fb.p[ro.slot_hist[1]];
+      P.s2 = A.fb.p[ro.slot_hist[2]];
+      P.mc = A.mb[ro.slot_m[0]];
+      P.mp = A.mb[ro.slot_m[1]];
     } else {
-      P.s0 = A.fb.p[A.ctl->slot_w[(A.ell - 1) & 1]];
+      P.s0 = A.fb.p[ro.slot_w[(A.ell - 1) & 1]];
     }
-    dst = A.fb.p[A.ctl->slot_w[A.ell & 1]];
+    dst = A.fb.p[ro.slot_w[A.ell & 1]];
   }
   if (A.did_run && blockIdx.x == 0 && threadIdx.x == 0) *A.did_run = 1;
 
@@ -631,14 +674,12 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
   }
 }
 
-// One block: FP64 sum of the sweep's block partials in a fixed order, then
-// the acceptance test.  A separate launch, so the partials written by blocks
-// on every XCD are visible through the kernel boundary (a per-block
-// agent-scope fence would write back the L2 after every block).
+// Large sweep grids: one block first folds the partials into partials_out[0]
+// (fixed order), so that the decision kernel's blocks each read one value.
 template <int UNUSED = 0>
-__global__ __launch_bounds__(256) void k_finish(FinishArgs A, const double* __restrict__ partials, int nparts) {
+__global__ __launch_bounds__(256) void k_presum(const double* __restrict__ partials, int nparts,
+                                                double* __restrict__ out) {
   __shared__ double red[256];
-  if (!phase_ready(A.ctl->phase, A.n, A.ell)) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < nparts; i += 256) acc += partials[i];
   red[threadIdx.x] = acc;
@@ -647,7 +688,7 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs A, const double* __re
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) finish_accept(A, red[0]);
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 }  // namespace msc
