@@ -368,12 +368,27 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
     }
   }
   CT M[4] = {0, 0, 0, 0};
+  if constexpr (DV) {
+    // deviation storage keeps P f itself: combine the stored FP32 moments
+    // (P of the rebuild is exactly M; P of the lift E dm is dm)
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    M[0] += f[k];
+    for (int b = 0; b <= D; ++b) {
+      if constexpr (MODE == SW_DTS_SETUP)
+        M[b] = (A.order == 0) ? r.M0[b]
+                              : (A.order == 1 ? (CT)2 * r.M0[b] - r.M1[b]
+                                              : (CT)3 * r.M0[b] - (CT)3 * r.M1[b] + r.M2[b]);
+      else
+        M[b] = r.M0[b];
+      if constexpr (MODE == SW_DTS_LIFT) M[b] += (CT)r.dmv[b];
+    }
+  } else {
 #pragma unroll
-    for (int b = 0; b < D; ++b)
-      if (ca<L>(k, b) != 0) M[1 + b] += (CT)ca<L>(k, b) * f[k];
+    for (int k = 0; k < Q; ++k) {
+      M[0] += f[k];
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        if (ca<L>(k, b) != 0) M[1 + b] += (CT)ca<L>(k, b) * f[k];
+    }
   }
   CT m[4], s[4];
   if (MODE == SW_EXPLICIT) {

@@ -8,7 +8,7 @@ The error is measured and bounded per result:
 * marches (replayed inner counts): RMS velocity error relative to the FP64
   oracle <= 1e-5, the FP32 bar (at omega+ = omega- = 1 the collision sees the
   populations only through their moments, which the storage keeps in FP32 and
-  the rebuild preserves exactly);
+  the sweep reads directly);
 * the explicit march: the same velocity bar.
 """
 import math
@@ -109,7 +109,7 @@ def test_fp16dev_free_running_march(M, orc):
     """Own acceptance decisions.  TGV at rho0 = 1 puts the FP32 floor of the
     raw residual near 1e-8, so eps = 1e-7; the FP16-deviation run takes the
     oracle's inner counts and its velocity error is stated beside FP32's
-    (measured 1.4e-5 and 7.9e-6)."""
+    (measured 9.5e-6 and 7.9e-6)."""
     N = 64
     p0, u0 = W.tgv2d(N, NU / N, NU)
     nsteps = 10
