@@ -52,9 +52,10 @@ def stokes_decay(u0, t, nu):
 
 
 def sweep_beyond_cache(msc, stream, torch, NL=4096):
-    """Sweep kernel bandwidth at N = 4096 (two 604 MB FP32 population arrays,
-    beyond the 256 MB last-level cache), explicit and dual-time modes, and a
-    plain device copy of 1.2 GB as the practical ceiling of this GPU."""
+    """Sweep kernel bandwidth beyond the 256 MB last-level cache: D2Q9 at
+    N = 4096 (two 604 MB FP32 population arrays), explicit and dual-time
+    modes; D3Q19 at N = 256^3 (two 1.27 GB arrays), explicit; and a plain
+    device copy of 1.2 GB (torch) as a reference ceiling."""
     pz = np.zeros((NL, NL))
     uz = np.zeros((2, NL, NL))
     uz[0] = 1e-4 * np.sin(2 * np.pi * np.arange(NL) / NL)[None, :]
@@ -68,6 +69,19 @@ def sweep_beyond_cache(msc, stream, torch, NL=4096):
     big.bdf2_step(1, raise_on_fail=False)
     ds, dn, db = big.kernel_time(0)
     big.close()
+    # D3Q19 N = 256^3: two 1.27 GB FP32 population arrays, explicit sweep
+    N3 = 256
+    p3 = msc.make_params(3, N3, dt=64.0, eps=1e-30, storage="fp32", corrector="picard", k_max=4)
+    z3 = torch.zeros((N3, N3, N3), dtype=torch.float64, device="cuda")
+    u3 = torch.zeros((3, N3, N3, N3), dtype=torch.float64, device="cuda")
+    u3[0] = 1e-4 * torch.sin(2 * math.pi * torch.arange(N3, dtype=torch.float64, device="cuda") / N3)[None, None, :]
+    big3 = msc.Solver(p3, z3, u3, stream=stream)
+    big3.explicit_step(2)
+    big3.set_kernel_timing(True)
+    big3.explicit_step(10)
+    ys, yn, yb = big3.kernel_time(1)
+    big3.close()
+    del z3, u3
     a = torch.empty(150 * 1024 * 1024, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
@@ -87,8 +101,73 @@ def sweep_beyond_cache(msc, stream, torch, NL=4096):
                      "frac": xb / (xs / xn) / 1e9 / HBM_PEAK_GBS},
         "dts": {"avg_launch_us": ds / dn * 1e6, "bytes_per_launch": db, "achieved_GBs": db / (ds / dn) / 1e9,
                 "frac": db / (ds / dn) / 1e9 / HBM_PEAK_GBS, "launches": dn},
+        "d3q19_n256_explicit": {"avg_launch_us": ys / yn * 1e6, "bytes_per_launch": yb,
+                                "achieved_GBs": yb / (ys / yn) / 1e9, "frac": yb / (ys / yn) / 1e9 / HBM_PEAK_GBS},
         "device_copy": {"bytes": copy_bytes, "avg_us": copy_s * 1e6, "achieved_GBs": copy_bytes / copy_s / 1e9,
                         "frac": copy_bytes / copy_s / 1e9 / HBM_PEAK_GBS},
+    }
+
+
+def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=None):
+    """Corrected march against the explicit march (same kernel, same storage)
+    over the workload's whole horizon, both timed; accuracy against an FP64
+    explicit endpoint (cached per workload)."""
+    cfg = W.config(name)
+    N, nu, d = cfg["N"], cfg["nu"], cfg["d"]
+    p0, u0 = W.initial_fields(cfg)
+    T_end, S, dt = cfg["T_end"], cfg["S"], cfg["dt"]
+    tnu = N * N / nu
+
+    def solver(st, corrector, eps=cfg["eps"]):
+        p = msc.make_params(d, N, dt=dt, eps=eps, storage=st, corrector=corrector, n_min=cfg["nmin"],
+                            extrap_states=extrap)
+        return msc.Solver(p, p0, u0, stream=stream)
+
+    if ref_cache is not None and name in ref_cache:
+        u_ref = ref_cache[name]
+    else:
+        r = solver("fp64", "picard")
+        r.explicit_step(int(T_end))
+        u_ref = r.moments()[1:]
+        r.close()
+        if ref_cache is not None:
+            ref_cache[name] = u_ref
+    e = solver(storage, "picard")
+    e.explicit_step(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.explicit_step(int(T_end) - 64)
+    torch.cuda.synchronize()
+    t_exp = (time.perf_counter() - t0) * T_end / (T_end - 64)
+    u_exp = e.moments()[1:]
+    e.close()
+    s = solver(storage, "shadow")
+    s.bdf2_step(2)
+    s.close()
+    s = solver(storage, "shadow")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, stats = s.bdf2_step(S, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t_msc = time.perf_counter() - t0
+    u_msc = s.moments()[1:]
+    s.close()
+    iters = [x["iters"] for x in stats]
+    e_msc = rms(u_msc - u_ref) / max(rms(u_ref), 1e-300)
+    e_exp = rms(u_exp - u_ref) / max(rms(u_ref), 1e-300)
+    Q = 9 if d == 2 else 19
+    bsite = {"fp64": 16 * Q, "fp32": 8 * Q, "fp16dev": 4 * Q + 8 * (d + 1)}[storage]
+    log(f"[bench] {name} {storage}: MSC {t_msc:.3f} s ({S} steps, inner {np.mean(iters):.2f}), explicit "
+        f"{t_exp:.2f} s, speedup {t_exp / t_msc:.1f}; errors MSC {e_msc:.3e} explicit {e_exp:.3e}")
+    return {
+        "lattice": "D2Q9" if d == 2 else "D3Q19", "N": N, "Re": cfg["Re"], "storage": storage, "dt": dt,
+        "eps": cfg["eps"], "n_min": cfg["nmin"], "extrap_states": extrap, "physical_steps": S,
+        "horizon_lattice_steps": T_end, "status": int(rc),
+        "msc_wall_s_per_viscous_time": t_msc * tnu / T_end, "explicit_wall_s_per_viscous_time": t_exp * tnu / T_end,
+        "speedup_vs_explicit": t_exp / t_msc, "mean_inner": float(np.mean(iters)), "max_inner": int(max(iters)),
+        "msc_rel_vs_fp64_explicit": e_msc, "explicit_rel_vs_fp64_explicit": e_exp,
+        "gate_1pct": e_msc <= 1e-2, "msc_not_less_accurate_than_explicit": e_msc <= e_exp,
+        "explicit_sweep_GBs": bsite * N ** d / (t_exp / T_end) / 1e9,
     }
 
 
@@ -104,6 +183,8 @@ def main():
                     help="population states in the initial-trial extrapolation (0: paper rule, up to cubic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the beyond-cache sweep measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the N=1024 (FP32, FP16 deviation) and D3Q19 N=128 workloads")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only the beyond-cache sweep measurement and a plain-copy calibration (profiling runs)")
     args = ap.parse_args()
@@ -256,7 +337,18 @@ def main():
         out["sweep_beyond_cache"] = sweep_beyond_cache(msc, stream, torch)
         sb = out["sweep_beyond_cache"]
         log(f"[bench] N=4096 sweep: explicit {sb['explicit']['achieved_GBs']:.0f} GB/s, dts "
-            f"{sb['dts']['achieved_GBs']:.0f} GB/s; device copy {sb['device_copy']['achieved_GBs']:.0f} GB/s")
+            f"{sb['dts']['achieved_GBs']:.0f} GB/s; D3Q19 N=256 explicit {sb['d3q19_n256_explicit']['achieved_GBs']:.0f}"
+            f" GB/s; device copy {sb['device_copy']['achieved_GBs']:.0f} GB/s")
+
+    # ---- the other workloads of the method (speedup at matched accuracy)
+    if not args.no_extras:
+        cache = {}
+        out["workloads"] = {
+            "rand2d_n1024_fp32": extra_workload(msc, W, stream, torch, "rand2d_n1024_fp32", "fp32", ref_cache=cache),
+            "rand2d_n1024_fp16dev": extra_workload(msc, W, stream, torch, "rand2d_n1024_fp32", "fp16dev",
+                                                   ref_cache=cache),
+            "tgv3d_n128_fp32": extra_workload(msc, W, stream, torch, "tgv3d_n128_fp32", "fp32"),
+        }
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:

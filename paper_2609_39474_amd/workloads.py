@@ -192,14 +192,17 @@ def config(name: str):
                     eps=1e-8, nmin=2, storage="fp32", kind="rand2d", seed=1)
     if name == "rand2d_n1024_fp32":
         N, Re = 1024, 1.0
-        T_end, S, dt = horizon(0.1, N, nu, 4915.2)
+        T_end, S, dt = horizon(0.1, N, nu, 9830.4)
         return dict(name=name, d=2, N=N, Re=Re, U=Re * nu / N, nu=nu, T_end=T_end, S=S, dt=dt,
                     eps=1e-8, nmin=2, storage="fp32", kind="rand2d", seed=1)
     if name == "tgv3d_n128_fp32":
         N, Re = 128, 1.0
         T_end, S, dt = horizon(0.1, N, nu, 64.0)
+        # n_min = 2 (the paper's 3D control is 1): over this horizon the field
+        # decays by about five decades and one-sweep acceptances under the
+        # absolute tolerance lose the solution
         return dict(name=name, d=3, N=N, Re=Re, U=Re * nu / N, nu=nu, T_end=T_end, S=S, dt=dt,
-                    eps=1e-8, nmin=1, storage="fp32", kind="tgv3d_pert", seed=1)
+                    eps=1e-8, nmin=2, storage="fp32", kind="tgv3d_pert", seed=1)
     if name == "vort2d_n256_adjoint":
         # differentiable march: vorticity control (seed 1), target from the
         # march of the seed-2 control, 20 steps of dt = 64
