@@ -108,6 +108,39 @@ def sweep_beyond_cache(msc, stream, torch, NL=4096):
     }
 
 
+def counter_traffic(path=os.path.join(ROOT, "profiles", "hbm_traffic_sweep_d2q9_n256_fp32.md")):
+    """HBM bytes per sweep launch of the default workload from the committed
+    FETCH_SIZE/WRITE_SIZE summary, or None when the sweep kernel's sources
+    have changed since those counters were taken (or the summary is absent)."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(path):
+            line = line.strip().lstrip("- ")
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for f in fields["kernel_sources"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != fields["kernel_source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def calibration_copies(torch):
+    """Five elementwise kernels b = 2 a over 64 MiB (a kernel of known
+    traffic: 64 MiB read, 64 MiB written)."""
+    a = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    return a.numel() * 4
+
+
 def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=None):
     """Corrected march against the explicit march (same kernel, same storage)
     over the workload's whole horizon, both timed; accuracy against an FP64
@@ -185,6 +218,10 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the beyond-cache sweep measurement")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the N=1024 (FP32, FP16 deviation) and D3Q19 N=128 workloads")
+    ap.add_argument("--march-only", action="store_true",
+                    help="only the timed corrected march and its sweep timing pass (counter runs)")
+    ap.add_argument("--calib", action="store_true",
+                    help="end with five 64 MiB device copies (a known-size kernel for counter calibration)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only the beyond-cache sweep measurement and a plain-copy calibration (profiling runs)")
     args = ap.parse_args()
@@ -251,6 +288,13 @@ def main():
     sweep_avg = sec / max(launches, 1)
     sweep_gbs = bytes_per / sweep_avg / 1e9 if launches else float("nan")
     log(f"[bench] sweep: {launches} launches, avg {sweep_avg * 1e6:.2f} us, {bytes_per / 1e6:.2f} MB -> {sweep_gbs:.0f} GB/s")
+    if args.march_only:
+        part = {"workload": args.workload, "steps": K, "msc_s": t_msc, "sweep_launches": launches,
+                "sweep_avg_us": sweep_avg * 1e6, "sweep_bytes_per_launch": bytes_per}
+        if args.calib:
+            part["calibration_copy_bytes_each_way"] = calibration_copies(torch)
+        print(json.dumps(part), flush=True)
+        return
 
     # ---- explicit baseline: same sweep kernel, same storage, same horizon
     nexp = int(round(T_sim))
@@ -325,7 +369,8 @@ def main():
         "inner_iterations": {"mean": float(np.mean(iters)), "max": int(max(iters)), "min": int(min(iters)),
                              "rho_obs_median": float(np.median(rhos)) if rhos else None},
         "roofline": {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": sweep_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": sweep_gbs / HBM_PEAK_GBS,
+                     "traffic": counter_traffic() if args.workload == "rand2d_n256_fp32" else None,
                      "kernel": "k_sweep (fused DTS sweep, lift + residual + P r)",
                      "bytes_per_launch": bytes_per, "avg_launch_us": sweep_avg * 1e6, "launches": launches},
         "explicit_sweep": {"avg_launch_us": xsec / max(xl, 1) * 1e6, "bytes_per_launch": xbytes,
@@ -374,6 +419,9 @@ def main():
             "mean_inner_iterations": float(np.mean(its)),
         }
         log(f"[bench] oracle: {t_cpu:.2f} s for {nsamp} steps")
+
+    if args.calib:
+        out["calibration_copy_bytes_each_way"] = calibration_copies(torch)
 
     print(json.dumps(out), flush=True)
 

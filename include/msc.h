@@ -261,8 +261,10 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
  * the sweep (0 = automatic), key 2 = physical steps enqueued per
  * host synchronisation (>= 1, default 32), 3 = speculative inner iterations
  * enqueued beyond the previous step's count (>= 0, default 0), 4 = capture
- * explicit-march chunks in HIP graphs (0/1, default 1).  Results do not
- * depend on these.  MSC_ERR_INVALID_ARG for an unknown key. */
+ * explicit-march chunks in HIP graphs (0/1, default 1), 5 = sweep tile by
+ * its 1-based position in the library's tile table (0 = automatic; overrides
+ * key 0).  Results do not depend on these.  MSC_ERR_INVALID_ARG for an
+ * unknown key. */
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);
 
 #ifdef __cplusplus

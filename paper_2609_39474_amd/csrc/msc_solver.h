@@ -30,6 +30,7 @@ struct Tuning {
   int batch_steps = 32;   // physical steps enqueued between host synchronisations
   int spec_extra = 0;     // speculative iterations beyond the last step's count
   int use_graph = 1;      // capture explicit chunks in hipGraphs
+  int sweep_tile_index = 0;  // 1-based entry of the tile table, 0 = automatic
 };
 
 class SolverBase {

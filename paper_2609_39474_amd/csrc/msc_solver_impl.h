@@ -10,6 +10,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "msc_adjoint.h"
 #include "msc_solver.h"
 
@@ -48,47 +50,62 @@ struct TileSet<D2Q9> {
 };
 template <>
 struct TileSet<D3Q19> {
-  static constexpr int count = 4;
+  static constexpr int count = 7;
   static TileCfg get(int i) {
-    const TileCfg t[4] = {{4, 4, 16}, {8, 8, 64}, {16, 16, 256}, {8, 32, 256}};
+    const TileCfg t[7] = {{4, 4, 16}, {8, 8, 64}, {16, 16, 256}, {8, 32, 256}, {4, 64, 256}, {2, 128, 256},
+                          {1, 256, 256}};
     return t[i];
   }
 };
 
-template <class L, class T, class TM, int NT, int T1, int T2>
-void launch_sweep_tile(int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st) {
-  if (mode == SW_EXPLICIT)
-    hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_EXPLICIT>), dim3(grid), dim3(NT), 0, st, A);
-  else if (mode == SW_DTS)
-    hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_DTS>), dim3(grid), dim3(NT), 0, st, A);
-  else if (mode == SW_DTS_LIFT)
-    hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_DTS_LIFT>), dim3(grid), dim3(NT), 0, st, A);
+// With ev0/ev1 the launch carries its own start/stop timestamps (kernel
+// timing), which adds no packets between this launch and its neighbours.
+template <class L, class T, class TM, int NT, int T1, int T2, int MODE>
+void launch_sweep_mode(const SweepArgs<T, TM>& A, int grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, MODE>), dim3(grid), dim3(NT), 0, st, ev0, ev1, 0, A);
   else
-    hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, SW_DTS_SETUP>), dim3(grid), dim3(NT), 0, st, A);
+    hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, MODE>), dim3(grid), dim3(NT), 0, st, A);
 }
 
-template <class L, class T, class TM>
-void launch_sweep(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st);
+template <class L, class T, class TM, int NT, int T1, int T2>
+void launch_sweep_tile(int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st, hipEvent_t ev0,
+                       hipEvent_t ev1) {
+  if (mode == SW_EXPLICIT)
+    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_EXPLICIT>(A, grid, st, ev0, ev1);
+  else if (mode == SW_DTS)
+    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS>(A, grid, st, ev0, ev1);
+  else if (mode == SW_DTS_LIFT)
+    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_LIFT>(A, grid, st, ev0, ev1);
+  else
+    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_SETUP>(A, grid, st, ev0, ev1);
+}
+
 
 template <class T, class TM>
-void launch_sweep_d2(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st) {
+void launch_sweep_d2(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   switch (tile) {
-    case 0: launch_sweep_tile<D2Q9, T, TM, 4, 1, 4>(mode, A, grid, st); break;
-    case 1: launch_sweep_tile<D2Q9, T, TM, 8, 1, 8>(mode, A, grid, st); break;
-    case 2: launch_sweep_tile<D2Q9, T, TM, 16, 1, 16>(mode, A, grid, st); break;
-    case 3: launch_sweep_tile<D2Q9, T, TM, 32, 1, 32>(mode, A, grid, st); break;
-    case 4: launch_sweep_tile<D2Q9, T, TM, 64, 1, 64>(mode, A, grid, st); break;
-    case 5: launch_sweep_tile<D2Q9, T, TM, 128, 1, 128>(mode, A, grid, st); break;
-    default: launch_sweep_tile<D2Q9, T, TM, 256, 1, 256>(mode, A, grid, st); break;
+    case 0: launch_sweep_tile<D2Q9, T, TM, 4, 1, 4>(mode, A, grid, st, ev0, ev1); break;
+    case 1: launch_sweep_tile<D2Q9, T, TM, 8, 1, 8>(mode, A, grid, st, ev0, ev1); break;
+    case 2: launch_sweep_tile<D2Q9, T, TM, 16, 1, 16>(mode, A, grid, st, ev0, ev1); break;
+    case 3: launch_sweep_tile<D2Q9, T, TM, 32, 1, 32>(mode, A, grid, st, ev0, ev1); break;
+    case 4: launch_sweep_tile<D2Q9, T, TM, 64, 1, 64>(mode, A, grid, st, ev0, ev1); break;
+    case 5: launch_sweep_tile<D2Q9, T, TM, 128, 1, 128>(mode, A, grid, st, ev0, ev1); break;
+    default: launch_sweep_tile<D2Q9, T, TM, 256, 1, 256>(mode, A, grid, st, ev0, ev1); break;
   }
 }
 template <class T, class TM>
-void launch_sweep_d3(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st) {
+void launch_sweep_d3(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   switch (tile) {
-    case 0: launch_sweep_tile<D3Q19, T, TM, 16, 4, 4>(mode, A, grid, st); break;
-    case 1: launch_sweep_tile<D3Q19, T, TM, 64, 8, 8>(mode, A, grid, st); break;
-    case 2: launch_sweep_tile<D3Q19, T, TM, 256, 16, 16>(mode, A, grid, st); break;
-    default: launch_sweep_tile<D3Q19, T, TM, 256, 8, 32>(mode, A, grid, st); break;
+    case 0: launch_sweep_tile<D3Q19, T, TM, 16, 4, 4>(mode, A, grid, st, ev0, ev1); break;
+    case 1: launch_sweep_tile<D3Q19, T, TM, 64, 8, 8>(mode, A, grid, st, ev0, ev1); break;
+    case 2: launch_sweep_tile<D3Q19, T, TM, 256, 16, 16>(mode, A, grid, st, ev0, ev1); break;
+    case 3: launch_sweep_tile<D3Q19, T, TM, 256, 8, 32>(mode, A, grid, st, ev0, ev1); break;
+    case 4: launch_sweep_tile<D3Q19, T, TM, 256, 4, 64>(mode, A, grid, st, ev0, ev1); break;
+    case 5: launch_sweep_tile<D3Q19, T, TM, 256, 2, 128>(mode, A, grid, st, ev0, ev1); break;
+    default: launch_sweep_tile<D3Q19, T, TM, 256, 1, 256>(mode, A, grid, st, ev0, ev1); break;
   }
 }
 
@@ -1169,7 +1186,11 @@ class Solver : public SolverBase {
   void choose_sweep() {
     const int n = TileSet<L>::count;
     int best = -1;
-    if (tune.sweep_tile > 0) {
+    if (tune.sweep_tile_index > 0 && tune.sweep_tile_index <= n) {
+      const TileCfg t = TileSet<L>::get(tune.sweep_tile_index - 1);
+      if (t.T1 <= G.N1 && t.T2 <= G.N2) best = tune.sweep_tile_index - 1;
+    }
+    if (best < 0 && tune.sweep_tile > 0) {
       for (int i = 0; i < n; ++i) {
         const TileCfg t = TileSet<L>::get(i);
         if (t.T1 * t.T2 == tune.sweep_tile && t.T1 <= G.N1 && t.T2 <= G.N2) best = i;
@@ -1185,7 +1206,11 @@ class Solver : public SolverBase {
         const TileCfg t = TileSet<L>::get(i);
         if (t.T1 > G.N1 || t.T2 > G.N2) continue;
         if (wide_fits && t.NT < 64) continue;
-        if (D == 3 && t.T1 == 16 && G.N2 >= 32 && G.N1 >= 8) continue;  // 8 x 32 coalesces better
+        // 3D: 4 x 64 tiles where they fit (fewer partial-line halo columns than
+        // 8 x 32 or 16 x 16; measured best at N = 128 and 256), else 8 x 32
+        if (D == 3 && G.N2 >= 64 && G.N1 >= 4 && !(t.T1 == 4 && t.T2 == 64)) continue;
+        if (D == 3 && t.T1 == 16 && G.N2 >= 32 && G.N1 >= 8) continue;
+        if (D == 3 && t.T1 < 4) continue;
         // the largest tile that fits (measured best at every size; the strip
         // length below supplies the parallelism)
         best = i;
@@ -1196,14 +1221,15 @@ class Solver : public SolverBase {
     const int64_t tiles = (int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2);
     int Lp = tune.sweep_strip;
     if (Lp <= 0) {
-      // Longest strip that keeps >= 1024 blocks (2D) or >= 512 (3D, more
-      // work per site): short strips cut the per-block chain of plane steps,
-      // which bounds small grids; long ones cut the two halo planes per
-      // strip.  Measured optimum of the sweep at N = 256 ... 4096 (2D) and
-      // N = 64, 128 (3D).
+      // Longest strip (at most 64 planes in 2D, 32 in 3D) that keeps >= 1024
+      // blocks (2D) or >= 512 (3D, more work per site): short strips cut the
+      // per-block chain of plane steps, which bounds small grids; long ones
+      // cut the two halo planes per strip.  Measured optimum of the sweep at
+      // N = 256 ... 4096 (2D) and N = 64 ... 256 (3D).
       const int64_t target = (D == 2) ? 1024 : 512;
+      const int Lmax = (D == 2) ? 64 : 32;
       Lp = 1;
-      while (Lp < 64 && tiles * (G.N0 / (Lp * 2)) >= target) Lp *= 2;
+      while (Lp < Lmax && tiles * (G.N0 / (Lp * 2)) >= target) Lp *= 2;
     }
     Lp = std::min(Lp, G.N0);
     while (G.N0 % Lp) Lp >>= 1;
@@ -1303,15 +1329,13 @@ class Solver : public SolverBase {
       ep.flag = (int)ev_live.size();
       ep.bytes = sweep_bytes(mode, S.order, S.q);
       S.did_run = run_flags + ep.flag;
-      MSC_HIPCK(hipEventRecord(ep.a, st));
     }
     if (D == 2)
-      launch_sweep_d2<T, TM>(tile_id, mode, S, sweep_grid(), st);
+      launch_sweep_d2<T, TM>(tile_id, mode, S, sweep_grid(), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
     else
-      launch_sweep_d3<T, TM>(tile_id, mode, S, sweep_grid(), st);
+      launch_sweep_d3<T, TM>(tile_id, mode, S, sweep_grid(), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
     MSC_HIPCK(hipGetLastError());
     if (timing) {
-      MSC_HIPCK(hipEventRecord(ep.b, st));
       ev_live.push_back(ep);
       if ((int)ev_live.size() >= kFlagCap) collect_timing();
     }
