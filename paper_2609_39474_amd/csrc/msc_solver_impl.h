@@ -237,8 +237,11 @@ class Solver : public SolverBase {
             want = std::max(P.n_min, last_iters + tune.spec_extra);
           int ell1 = (ell0 == 1) ? want : ell0 - 1 + std::max(8, want);
           ell1 = std::min(std::max(ell1, ell0), P.k_max);
+          // resuming a step: the previous batch ended it at sweep ell0 - 1
+          // without the correction's later passes
+          if (ell0 > 1) enqueue_correction_tail(n, ell0 - 1, a);
           for (int ell = ell0; ell <= ell1; ++ell)
-            enqueue_iteration(n, ell, q, order, a, use_sched, stat_base);
+            enqueue_iteration(n, ell, q, order, a, use_sched, stat_base, ell == ell1);
         }
         MSC_HIPCK(hipMemcpyAsync(ctl_h, ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
         sync();
@@ -1371,7 +1374,11 @@ class Solver : public SolverBase {
   // device: the sweep (the first one of a step also forms h_q and the
   // extrapolated trial), the one-block acceptance test, then either the
   // reconstruction of m^{n+1} (accepted) or the shadow correction.
-  void enqueue_iteration(int n, int ell, int q, int order, double a, bool use_sched, int stat_base) {
+  // last: the final iteration enqueued for this step; its correction passes
+  // after the first are left out (they run only if the step goes on, and then
+  // enqueue_correction_tail supplies them before the next sweep).
+  void enqueue_iteration(int n, int ell, int q, int order, double a, bool use_sched, int stat_base,
+                         bool last = false) {
     SweepArgs<T, TM> S = sweep_args(a);
     S.ctl = ctl;
     S.n = n;
@@ -1413,11 +1420,20 @@ class Solver : public SolverBase {
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
     if (P.corrector == MSC_CORRECTOR_SHADOW) {
       XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
-      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F);
+      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last);
     } else {
       hipLaunchKernelGGL((k_accept<L, T>), dim3(ew_grid()), dim3(256), 0, st, Ac, F);
       MSC_HIPCK(hipGetLastError());
     }
+  }
+
+  // The correction passes after the first for (step n, sweep ell), guarded on
+  // the device (they run only if that sweep was not accepted).
+  void enqueue_correction_tail(int n, int ell, double a) {
+    if (P.corrector != MSC_CORRECTOR_SHADOW) return;
+    XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
+    AcceptArgs<L, T> Ac = accept_args(n, ell, a);
+    enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, nullptr, false, true);
   }
 
   AcceptArgs<L, T> accept_args(int n, int ell, double a) {
@@ -1509,7 +1525,8 @@ class Solver : public SolverBase {
 
   template <class CX, class TX>
   void enqueue_transform(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac, bool adjoint,
-                         const XformBufs<CX, TX>& B, const FinishArgs* Fin = nullptr) {
+                         const XformBufs<CX, TX>& B, const FinishArgs* Fin = nullptr, bool head = true,
+                         bool tail = true) {
     AcceptArgs<L, T> none{};
     const FinishArgs nofin{};
     const size_t cb = sizeof(cpx<CX>);
@@ -1537,13 +1554,17 @@ class Solver : public SolverBase {
       const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
       const int grows = G.N0 / F.rows_per_block;
       const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
-      hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CX, TX>), dim3(grows), dim3(256), rows_b, st, F, Ac ? *Ac : none,
-                         Fin ? *Fin : nofin);
-      MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft2_cols_solve<CX, TX>), dim3(gcols), dim3(256), cols_b, st, F);
-      MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft2_rows_inv<CX, TX>), dim3(grows), dim3(256), rows_b, st, F);
-      MSC_HIPCK(hipGetLastError());
+      if (head) {
+        hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CX, TX>), dim3(grows), dim3(256), rows_b, st, F,
+                           Ac ? *Ac : none, Fin ? *Fin : nofin);
+        MSC_HIPCK(hipGetLastError());
+      }
+      if (tail) {
+        hipLaunchKernelGGL((k_fft2_cols_solve<CX, TX>), dim3(gcols), dim3(256), cols_b, st, F);
+        MSC_HIPCK(hipGetLastError());
+        hipLaunchKernelGGL((k_fft2_rows_inv<CX, TX>), dim3(grows), dim3(256), rows_b, st, F);
+        MSC_HIPCK(hipGetLastError());
+      }
     } else {
       Fft3Args<CX, TX> F{};
       F.g = CorrGuard{c, n, ell};
@@ -1575,9 +1596,12 @@ class Solver : public SolverBase {
       const size_t xb = 8 * (size_t)JB * F.Nx * cb;
       const int ng = (F.NBz + JB - 1) / JB;
       const int gz = (int)(((int64_t)F.Nx * F.Ny) / R);
-      hipLaunchKernelGGL((k_fft3_z_fwd<L, T, CX, TX>), dim3(gz), dim3(256), zb, st, F, Ac ? *Ac : none,
-                         Fin ? *Fin : nofin);
-      MSC_HIPCK(hipGetLastError());
+      if (head) {
+        hipLaunchKernelGGL((k_fft3_z_fwd<L, T, CX, TX>), dim3(gz), dim3(256), zb, st, F, Ac ? *Ac : none,
+                           Fin ? *Fin : nofin);
+        MSC_HIPCK(hipGetLastError());
+      }
+      if (!tail) return;
       hipLaunchKernelGGL((k_fft3_y_fwd<CX, TX>), dim3(F.Nx * ng), dim3(256), yb, st, F);
       MSC_HIPCK(hipGetLastError());
       hipLaunchKernelGGL((k_fft3_x_solve<CX, TX>), dim3(F.NBy * ng), dim3(256), xb, st, F);
