@@ -137,7 +137,7 @@ __device__ inline void finish_commit(const FinishArgs& A, double R, int dec, int
 
 // Block-uniform decision for (step n, sweep ell), or DEC_SKIP when the march
 // is not right after that sweep.  The phase word is either still the one the
-// sweep saw or already block 0's record of this very decision.  Uses red[256].
+// sweep saw or already block 0's record of this very decision.  Uses red[] (one entry per wavefront).
 __device__ inline int finish_block(const FinishArgs& A, double* red) {
   __shared__ int sh_mine;
   if (threadIdx.x == 0) {
@@ -147,15 +147,17 @@ __device__ inline int finish_block(const FinishArgs& A, double* red) {
   }
   __syncthreads();
   if (!sh_mine) return DEC_SKIP;
+  // fixed-order fold: strided per thread, then within each wavefront by
+  // shuffles, then across the (blockDim / 64) wavefronts in order
   double acc = 0.0;
   for (int i = threadIdx.x; i < A.nparts; i += blockDim.x) acc += A.partials[i];
-  red[threadIdx.x] = acc;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double R = sqrt(red[0] * A.inv_count);
+  double tot = 0.0;
+  for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) tot += red[wv];
+  const double R = sqrt(tot * A.inv_count);
   int fail = 0;
   const int dec = accept_decision(A, R, &fail);
   if (blockIdx.x == 0 && threadIdx.x == 0) finish_commit(A, R, dec, fail);
