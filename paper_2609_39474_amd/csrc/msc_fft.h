@@ -18,94 +18,6 @@
 
 namespace msc {
 
-template <class CT>
-struct cpx {
-  CT x, y;
-};
-
-template <class CT>
-__device__ __forceinline__ cpx<CT> cmul(cpx<CT> a, cpx<CT> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <class CT>
-__device__ __forceinline__ cpx<CT> cadd(cpx<CT> a, cpx<CT> b) {
-  return {a.x + b.x, a.y + b.y};
-}
-template <class CT>
-__device__ __forceinline__ cpx<CT> csub(cpx<CT> a, cpx<CT> b) {
-  return {a.x - b.x, a.y - b.y};
-}
-// multiply by +i (s > 0) or -i (s < 0)
-template <class CT>
-__device__ __forceinline__ cpx<CT> cmuli(cpx<CT> a, int s) {
-  return s > 0 ? cpx<CT>{-a.y, a.x} : cpx<CT>{a.y, -a.x};
-}
-
-// nt independent transforms of length N = 2^lg stored contiguously at
-// buf + t*N.  sign = -1 forward, +1 inverse (no scaling).  The caller has
-// synchronised after filling buf; returns the array holding the result (buf
-// or tmp), synchronised.
-template <class CT>
-__device__ cpx<CT>* lds_fft(cpx<CT>* buf, cpx<CT>* tmp, int lg, int nt, int sign,
-                            const cpx<CT>* __restrict__ tw) {
-  const int N = 1 << lg;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  cpx<CT>* a = buf;
-  cpx<CT>* b = tmp;
-  int Ns = 1;
-  for (int p = 0; p < (lg >> 1); ++p) {
-    const int lnb = lg - 2, nb = 1 << lnb;
-    const int tstride = N / (4 * Ns);
-    for (int j = tid; j < (nt << lnb); j += nth) {
-      const int t = j >> lnb, jj = j & (nb - 1);
-      const cpx<CT>* x = a + t * N;
-      cpx<CT>* y = b + t * N;
-      const int k = jj & (Ns - 1);
-      cpx<CT> w1 = tw[k * tstride], w2 = tw[2 * k * tstride], w3 = tw[3 * k * tstride];
-      if (sign > 0) {
-        w1.y = -w1.y;
-        w2.y = -w2.y;
-        w3.y = -w3.y;
-      }
-      const cpx<CT> v0 = x[jj];
-      const cpx<CT> v1 = cmul(x[jj + nb], w1);
-      const cpx<CT> v2 = cmul(x[jj + 2 * nb], w2);
-      const cpx<CT> v3 = cmul(x[jj + 3 * nb], w3);
-      const cpx<CT> s02 = cadd(v0, v2), d02 = csub(v0, v2);
-      const cpx<CT> s13 = cadd(v1, v3), d13 = cmuli(csub(v1, v3), sign);
-      const int base = ((jj - k) << 2) + k;
-      y[base] = cadd(s02, s13);
-      y[base + Ns] = cadd(d02, d13);
-      y[base + 2 * Ns] = csub(s02, s13);
-      y[base + 3 * Ns] = csub(d02, d13);
-    }
-    __syncthreads();
-    cpx<CT>* sw = a;
-    a = b;
-    b = sw;
-    Ns <<= 2;
-  }
-  if (lg & 1) {
-    const int lnb = lg - 1, nb = 1 << lnb;
-    const int tstride = N / (2 * Ns);
-    for (int j = tid; j < (nt << lnb); j += nth) {
-      const int t = j >> lnb, jj = j & (nb - 1);
-      const cpx<CT>* x = a + t * N;
-      cpx<CT>* y = b + t * N;
-      const int k = jj & (Ns - 1);
-      cpx<CT> w1 = tw[k * tstride];
-      if (sign > 0) w1.y = -w1.y;
-      const cpx<CT> v0 = x[jj];
-      const cpx<CT> v1 = cmul(x[jj + nb], w1);
-      const int base = ((jj - k) << 1) + k;
-      y[base] = cadd(v0, v1);
-      y[base + Ns] = csub(v0, v1);
-    }
-    __syncthreads();
-    a = b;
-  }
-  return a;
-}
 
 // Eq. (schur) at one wavevector, FP64.  r[0] = F[r_p], r[1..D] = F[r_m];
 // out[0] = dp, out[1..D] = du, each scaled by `scale` (the 1/N_Omega of the
@@ -181,6 +93,7 @@ template <class CT, class TM>
 struct Fft2Args {
   CorrGuard g;
   int do_accept;  // Algorithm 1 mode: the first pass decides acceptance (and reconstructs m^{n+1})
+  int decide;     // the row pass ran inside the sweep: the column pass decides instead
   int adjoint;    // apply chi H^{-H} (transpose of the correction) instead of chi H^{-1}
   int Nx, Ny, lgx, lgy;
   int NBy;      // N_y/4 + 1
@@ -243,9 +156,23 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A, Accep
 // Pass 2: for a group of j_y columns, forward transform along x, the FP64
 // Schur solve on the band |j_x| <= N_x/4 (zero elsewhere), and the inverse
 // transform along x, in place in the band spectrum array.
-template <class CT, class TM>
-__global__ __launch_bounds__(256) void k_fft2_cols_solve(Fft2Args<CT, TM> A) {
-  if (A.g.skip()) return;
+template <class L, class T, class CT, class TM>
+__global__ __launch_bounds__(256) void k_fft2_cols_solve(Fft2Args<CT, TM> A, AcceptArgs<L, T> Ac, FinishArgs Fin) {
+  if (A.decide) {
+    // Algorithm 1 with the row pass fused into the sweep: decide here; if
+    // accepted, reconstruct m^{n+1} over the whole field instead
+    __shared__ double red[4];
+    const int dec = finish_block(Fin, red);
+    if (dec != DEC_RUNNING) {
+      if (dec == DEC_ACCEPTED)
+        accept_sites<L, T>(Ac, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, Ac.NS,
+                           (int64_t)gridDim.x * blockDim.x);
+      return;
+    }
+    if ((int)blockIdx.x * A.cols_per_block >= A.NBy) return;  // reconstruction-only block
+  } else if (A.g.skip()) {
+    return;
+  }
   extern __shared__ unsigned char smem_raw[];
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
   const int Nx = A.Nx, JB = A.cols_per_block, NB = A.NBy;

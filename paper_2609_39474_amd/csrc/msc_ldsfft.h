@@ -1,0 +1,99 @@
+// Complex arithmetic and the radix-4 Stockham transform of lines held in
+// LDS, shared by the transform passes of the shadow correction and by the
+// sweep's fused forward row transform.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace msc {
+
+template <class CT>
+struct cpx {
+  CT x, y;
+};
+
+template <class CT>
+__device__ __forceinline__ cpx<CT> cmul(cpx<CT> a, cpx<CT> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class CT>
+__device__ __forceinline__ cpx<CT> cadd(cpx<CT> a, cpx<CT> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <class CT>
+__device__ __forceinline__ cpx<CT> csub(cpx<CT> a, cpx<CT> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+// multiply by +i (s > 0) or -i (s < 0)
+template <class CT>
+__device__ __forceinline__ cpx<CT> cmuli(cpx<CT> a, int s) {
+  return s > 0 ? cpx<CT>{-a.y, a.x} : cpx<CT>{a.y, -a.x};
+}
+
+// nt independent transforms of length N = 2^lg stored contiguously at
+// buf + t*N.  sign = -1 forward, +1 inverse (no scaling).  The caller has
+// synchronised after filling buf; returns the array holding the result (buf
+// or tmp), synchronised.
+template <class CT>
+__device__ cpx<CT>* lds_fft(cpx<CT>* buf, cpx<CT>* tmp, int lg, int nt, int sign,
+                            const cpx<CT>* __restrict__ tw) {
+  const int N = 1 << lg;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  cpx<CT>* a = buf;
+  cpx<CT>* b = tmp;
+  int Ns = 1;
+  for (int p = 0; p < (lg >> 1); ++p) {
+    const int lnb = lg - 2, nb = 1 << lnb;
+    const int tstride = N / (4 * Ns);
+    for (int j = tid; j < (nt << lnb); j += nth) {
+      const int t = j >> lnb, jj = j & (nb - 1);
+      const cpx<CT>* x = a + t * N;
+      cpx<CT>* y = b + t * N;
+      const int k = jj & (Ns - 1);
+      cpx<CT> w1 = tw[k * tstride], w2 = tw[2 * k * tstride], w3 = tw[3 * k * tstride];
+      if (sign > 0) {
+        w1.y = -w1.y;
+        w2.y = -w2.y;
+        w3.y = -w3.y;
+      }
+      const cpx<CT> v0 = x[jj];
+      const cpx<CT> v1 = cmul(x[jj + nb], w1);
+      const cpx<CT> v2 = cmul(x[jj + 2 * nb], w2);
+      const cpx<CT> v3 = cmul(x[jj + 3 * nb], w3);
+      const cpx<CT> s02 = cadd(v0, v2), d02 = csub(v0, v2);
+      const cpx<CT> s13 = cadd(v1, v3), d13 = cmuli(csub(v1, v3), sign);
+      const int base = ((jj - k) << 2) + k;
+      y[base] = cadd(s02, s13);
+      y[base + Ns] = cadd(d02, d13);
+      y[base + 2 * Ns] = csub(s02, s13);
+      y[base + 3 * Ns] = csub(d02, d13);
+    }
+    __syncthreads();
+    cpx<CT>* sw = a;
+    a = b;
+    b = sw;
+    Ns <<= 2;
+  }
+  if (lg & 1) {
+    const int lnb = lg - 1, nb = 1 << lnb;
+    const int tstride = N / (2 * Ns);
+    for (int j = tid; j < (nt << lnb); j += nth) {
+      const int t = j >> lnb, jj = j & (nb - 1);
+      const cpx<CT>* x = a + t * N;
+      cpx<CT>* y = b + t * N;
+      const int k = jj & (Ns - 1);
+      cpx<CT> w1 = tw[k * tstride];
+      if (sign > 0) w1.y = -w1.y;
+      const cpx<CT> v0 = x[jj];
+      const cpx<CT> v1 = cmul(x[jj + nb], w1);
+      const int base = ((jj - k) << 1) + k;
+      y[base] = cadd(v0, v1);
+      y[base + Ns] = csub(v0, v1);
+    }
+    __syncthreads();
+    a = b;
+  }
+  return a;
+}
+
+}  // namespace msc

@@ -1185,6 +1185,9 @@ class Solver : public SolverBase {
   // ------------------------------------------------------ sweep config --
   int tile_id = 0, strip_L = 1;
   TileCfg tile{};
+  // 2D with the shadow corrector and tiles spanning whole rows: the sweep
+  // also does the forward row transform of P r
+  bool fuse_rows = false;
 
   void choose_sweep() {
     const int n = TileSet<L>::count;
@@ -1237,6 +1240,8 @@ class Solver : public SolverBase {
     Lp = std::min(Lp, G.N0);
     while (G.N0 % Lp) Lp >>= 1;
     strip_L = std::max(Lp, 1);
+    fuse_rows = D == 2 && P.corrector == MSC_CORRECTOR_SHADOW && tile.T1 == 1 && tile.T2 == G.N2 &&
+                tile.NT == tile.T2 && corrector_supported() && tune.fuse_rows != 0;
   }
 
   int sweep_grid() const {
@@ -1278,6 +1283,8 @@ class Solver : public SolverBase {
     const double fb1 = (double)pop_bytes(), mb1 = (double)(D + 1) * NS;
     if (mode == SW_EXPLICIT) return 2.0 * fb1;
     double b = 2.0 * fb1 + mb1 * sizeof(TM);  // f in, f_T out, P r out
+    if (fuse_rows && (mode == SW_DTS_LIFT || mode == SW_DTS_SETUP))  // row spectrum out instead of P r
+      b += (double)(D + 1) * G.N0 * (G.N2 / 4 + 1) * sizeof(cpx<TM>) - mb1 * sizeof(TM);
     if (mode == SW_DTS_SETUP)
       b += order * fb1 + mb1 * sizeof(double) * (q == 2 ? 3.0 : 2.0);
     else
@@ -1408,6 +1415,13 @@ class Solver : public SolverBase {
       mode = SW_DTS_SETUP;
     else
       mode = (P.corrector == MSC_CORRECTOR_SHADOW) ? SW_DTS_LIFT : SW_DTS;
+    if (fuse_rows) {
+      S.fuse_rows = 1;
+      S.lgr = ilog2(G.N2);
+      S.NBr = G.N2 / 4 + 1;
+      S.spec = spec;
+      S.twr = tw[2];
+    }
     launch_sweep_timed(mode, S, 0);
     if (F.nparts > kFusedParts) {
       // many sweep blocks: fold the partials once instead of in every block
@@ -1420,7 +1434,7 @@ class Solver : public SolverBase {
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
     if (P.corrector == MSC_CORRECTOR_SHADOW) {
       XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
-      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last);
+      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last, fuse_rows);
     } else {
       hipLaunchKernelGGL((k_accept<L, T>), dim3(ew_grid()), dim3(256), 0, st, Ac, F);
       MSC_HIPCK(hipGetLastError());
@@ -1433,7 +1447,7 @@ class Solver : public SolverBase {
     if (P.corrector != MSC_CORRECTOR_SHADOW) return;
     XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
-    enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, nullptr, false, true);
+    enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, nullptr, false, true, fuse_rows);
   }
 
   AcceptArgs<L, T> accept_args(int n, int ell, double a) {
@@ -1494,7 +1508,7 @@ class Solver : public SolverBase {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
       MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_rows_inv<CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, rows_b));
-      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_cols_solve<CX, TX>,
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fft2_cols_solve<L, T, CX, TX>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, cols_b));
     } else {
       const int zb = (int)(4 * fft3_pencils_per_block(c) * G.n[2] * c);
@@ -1526,7 +1540,7 @@ class Solver : public SolverBase {
   template <class CX, class TX>
   void enqueue_transform(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac, bool adjoint,
                          const XformBufs<CX, TX>& B, const FinishArgs* Fin = nullptr, bool head = true,
-                         bool tail = true) {
+                         bool tail = true, bool rows_in_sweep = false) {
     AcceptArgs<L, T> none{};
     const FinishArgs nofin{};
     const size_t cb = sizeof(cpx<CX>);
@@ -1554,13 +1568,31 @@ class Solver : public SolverBase {
       const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
       const int grows = G.N0 / F.rows_per_block;
       const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
+      if (rows_in_sweep) {
+        // the sweep wrote the row spectrum; the column pass decides
+        F.do_accept = 0;
+        F.decide = 1;
+        if (head) {
+          // enough blocks for the reconstruction of an accepted step; blocks
+          // beyond the column count stop after the decision otherwise
+          const int gdec = std::max<int>(gcols, (int)std::min<int64_t>((G.NS + 255) / 256, 4096));
+          hipLaunchKernelGGL((k_fft2_cols_solve<L, T, CX, TX>), dim3(gdec), dim3(256), cols_b, st, F,
+                             Ac ? *Ac : none, Fin ? *Fin : nofin);
+          MSC_HIPCK(hipGetLastError());
+        }
+        if (tail) {
+          hipLaunchKernelGGL((k_fft2_rows_inv<CX, TX>), dim3(grows), dim3(256), rows_b, st, F);
+          MSC_HIPCK(hipGetLastError());
+        }
+        return;
+      }
       if (head) {
         hipLaunchKernelGGL((k_fft2_rows_fwd<L, T, CX, TX>), dim3(grows), dim3(256), rows_b, st, F,
                            Ac ? *Ac : none, Fin ? *Fin : nofin);
         MSC_HIPCK(hipGetLastError());
       }
       if (tail) {
-        hipLaunchKernelGGL((k_fft2_cols_solve<CX, TX>), dim3(gcols), dim3(256), cols_b, st, F);
+        hipLaunchKernelGGL((k_fft2_cols_solve<L, T, CX, TX>), dim3(gcols), dim3(256), cols_b, st, F, none, nofin);
         MSC_HIPCK(hipGetLastError());
         hipLaunchKernelGGL((k_fft2_rows_inv<CX, TX>), dim3(grows), dim3(256), rows_b, st, F);
         MSC_HIPCK(hipGetLastError());

@@ -24,6 +24,7 @@
 #include <type_traits>
 
 #include "msc_common.h"
+#include "msc_ldsfft.h"
 
 namespace msc {
 
@@ -189,6 +190,13 @@ struct SweepArgs {
   double* mb[3];
   int q, order;
   double dt;
+  // fused forward row transform (2D, tiles spanning whole rows, Algorithm 1
+  // with the shadow corrector): the band spectrum of P r goes to spec
+  // ([field][x][j <= N_y/4], as the first transform pass writes it) instead
+  // of P r to Pr
+  int fuse_rows, lgr, NBr;
+  cpx<TM>* spec;
+  const cpx<TM>* twr;
 };
 
 // ---- compile-time direction classification -----------------------------
@@ -458,6 +466,8 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
   // post-collision values travel through LDS in the storage type, or FP32
   // for deviation storage (they are full populations there)
   using LT = typename std::conditional<PopDev<T>::value, float, T>::type;
+  constexpr bool ROWFFT = (T1 == 1 && MODE != SW_EXPLICIT && NT == T2);
+  __shared__ cpx<CT> fbuf[ROWFFT ? 4 * T2 : 1];
   __shared__ LT ldsP[4][NGP][NI];
   __shared__ LT ldsZ[3][NG0][NI];
   __shared__ LT ldsM[2][NGM][NI];
@@ -653,8 +663,33 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
           }
         }
         if (MODE != SW_EXPLICIT) {
+          if (ROWFFT && A.fuse_rows) {
+            // the row of P r (fields 0 and 1 packed in one complex line, field 2 in a second)
+            fbuf[i2] = {pr[0], pr[1]};
+            fbuf[T2 + i2] = {pr[2], (CT)0};
+          } else {
 #pragma unroll
-          for (int bb = 0; bb <= D; ++bb) __builtin_nontemporal_store((TM)pr[bb], &A.Pr[bb * NS + site]);
+            for (int bb = 0; bb <= D; ++bb) __builtin_nontemporal_store((TM)pr[bb], &A.Pr[bb * NS + site]);
+          }
+        }
+      }
+      if constexpr (ROWFFT) {
+        if (A.fuse_rows) {
+          // forward transform along y of this plane's P r, band j <= N_y/4
+          // kept (Eq. fft-convention, shadow-mask); unpack the packed pair
+          __syncthreads();
+          const cpx<CT>* out = lds_fft<CT>(fbuf, fbuf + 2 * T2, A.lgr, 2, -1, A.twr);
+          const int NB = A.NBr;
+          const int64_t FS = (int64_t)N0 * NB;
+          for (int j = tid; j < NB; j += NT) {
+            const cpx<CT> z = out[j];
+            const cpx<CT> zc = out[(T2 - j) & (T2 - 1)];
+            const int64_t o = (int64_t)xd * NB + j;
+            A.spec[o] = {(CT)0.5 * (z.x + zc.x), (CT)0.5 * (z.y - zc.y)};
+            A.spec[FS + o] = {(CT)0.5 * (z.y + zc.y), (CT)0.5 * (zc.x - z.x)};
+            A.spec[2 * FS + o] = out[T2 + j];
+          }
+          __syncthreads();  // fbuf is refilled by the next plane
         }
       }
     }
