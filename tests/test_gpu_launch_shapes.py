@@ -1,0 +1,132 @@
+"""GPU parity of the launch-shape variants (through the C ABI, FP64 storage,
+against the FP64 oracle at 1e-12): the forward row transform fused into the
+sweep or run as its own pass, sweep tiles and strip lengths other than the
+automatic choice, the folded-partials path of large sweep grids, and every
+D3Q19 tile of the library's table.  Results must not depend on these choices
+beyond rounding order.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_39474_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NU = 1.0 / 6.0
+KEY_TILE, KEY_STRIP, KEY_TILE_INDEX, KEY_FUSE_ROWS = 0, 1, 5, 6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2609_39474_amd import msc
+    msc.lib()
+    return msc
+
+
+def _solver(M, shape, p0, u0, *, dt, eps=1e-10, n_min=2):
+    d = len(shape)
+    p = M.make_params(d, shape[0], dt=dt, eps=eps, n_min=n_min)
+    for a in range(d):
+        p.n[a] = shape[a]
+    return M.Solver(p, p0, u0)
+
+
+@pytest.mark.parametrize("fuse", [0, 1])
+def test_fused_row_transform_on_off(M, orc, fuse):
+    """2D TGV N = 64: twelve steps at the oracle's inner counts."""
+    cfg = W.config("tgv2d_n64_fp64")
+    N = cfg["N"]
+    p0, u0 = W.initial_fields(cfg)
+    ref = orc.march(p0, u0, dt=cfg["dt"], nsteps=12, eps=cfg["eps"], nmin=2)
+    K = [st["iters"] for st in ref.stats]
+    s = _solver(M, (N, N), p0, u0, dt=cfg["dt"], eps=cfg["eps"])
+    s.set_tuning(KEY_FUSE_ROWS, fuse)
+    s.set_schedule(K)
+    rc, stats = s.bdf2_step(12)
+    assert rc == 0 and [x["iters"] for x in stats] == K
+    e = rel(s.moments(), ref.m)
+    say("fuse_rows", fuse, "rel", e)
+    assert e <= 1e-12
+    s.close()
+
+
+SHAPES_2D = [
+    # (tile sites, strip planes): the automatic shape (fused row transform,
+    # one plane per strip); 4-site tiles with one-plane strips (16384 sweep
+    # blocks: the partials are folded by a separate kernel first); 64-site
+    # tiles (row transform as its own pass); whole rows with four-plane
+    # strips (fused, four row transforms per block)
+    (0, 0), (4, 1), (64, 2), (256, 4),
+]
+
+
+@pytest.fixture(scope="module")
+def ref256(orc):
+    N = 256
+    p0, u0 = W.random_field_2d(N, NU / N, seed=3)
+    ref = orc.march(p0, u0, dt=256.0, nsteps=3, eps=1e-10, nmin=2, extrap_states=2)
+    return p0, u0, ref
+
+
+@pytest.mark.parametrize("tile,strip", SHAPES_2D)
+def test_march_launch_shapes_2d(M, ref256, tile, strip):
+    p0, u0, ref = ref256
+    K = [st["iters"] for st in ref.stats]
+    p = M.make_params(2, 256, dt=256.0, eps=1e-10, extrap_states=2)
+    s = M.Solver(p, p0, u0)
+    s.set_tuning(KEY_TILE, tile)
+    s.set_tuning(KEY_STRIP, strip)
+    s.set_schedule(K)
+    rc, stats = s.bdf2_step(3)
+    assert rc == 0 and [x["iters"] for x in stats] == K
+    for a, b in zip(stats, ref.stats):
+        assert abs(a["R_final"] - b["R_final"]) <= 1e-9 * b["R_final"]
+    e = rel(s.moments(), ref.m)
+    say("2D tile", tile, "strip", strip, "rel", e)
+    assert e <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3, 4, 5, 6, 7])
+def test_d3q19_tiles(M, orc, idx):
+    """Every D3Q19 tile of the table on a grid they all fit (8 x 16 x 256):
+    one corrected iteration and one BDF step at the oracle's count."""
+    shape = (8, 16, 256)
+    rng = np.random.default_rng(idx)
+    c, w, _ = orc.lattice(3)
+    wq = w.reshape((19, 1, 1, 1))
+    f = wq * (1e-3 * rng.normal(size=(19,) + shape)) + wq * 0.01 * rng.normal(size=shape)
+    h = 1e-4 * rng.normal(size=(4,) + shape)
+    a = 3.0 / 128.0
+    p0 = np.zeros(shape)
+    u0 = np.zeros((3,) + shape)
+    s = _solver(M, shape, p0, u0, dt=16.0, n_min=1)
+    s.set_tuning(KEY_TILE_INDEX, idx)
+    fn, dm, R = s.correct(f, h, a)
+    ofn, _, _, odm, oR = orc.corrected_iteration(f, h, a, 1.0, 1.0, NU)
+    assert rel(dm, odm) <= 1e-12 and rel(fn, ofn) <= 1e-12 and abs(R - oR) <= 1e-12 * oR
+    # one BDF step from a smooth state
+    u1 = W.random_perturbation_3d(8, 1e-3, seed=idx, jmax=2)
+    u1 = np.tile(u1, (1, 1, 2, 32))
+    st0 = orc.initial_state(p0, u1)
+    rc, st1, bc1, ost = orc.march_state(st0, 0, shape, dt=16.0, nsteps=1, eps=1e-10, nmin=1)
+    s.set_state(st0, 0)
+    s.set_schedule([ost[0]["iters"]])
+    rc, gst = s.bdf2_step(1)
+    assert rc == 0 and gst[0]["iters"] == ost[0]["iters"]
+    g, _ = s.get_state()
+    say("3D tile index", idx, "correct", rel(fn, ofn), "step", rel(g, st1))
+    assert rel(g, st1) <= 1e-12
+    s.close()
