@@ -204,6 +204,57 @@ def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=Non
     }
 
 
+def adjoint_workload(msc, W, stream, torch):
+    """Differentiable march of the vorticity-control workload (D2Q9 N=256,
+    20 steps of dt=64, FP32): forward march, forward with per-step
+    checkpoints, and the backward pass (msc_bdf2_adjoint) timed on the GPU."""
+    from paper_2609_39474_amd import autograd as AG
+
+    cfg = W.config("vort2d_n256_adjoint")
+    N, nsteps, dt = cfg["N"], cfg["nsteps"], cfg["dt"]
+    w0 = torch.tensor(W.random_vorticity_2d(N, cfg["U"], seed=cfg["seed"]), device="cuda")
+    u0 = AG.biot_savart(w0).contiguous()
+    p0 = torch.zeros((N, N), dtype=torch.float64, device="cuda")
+
+    def solver():
+        p = msc.make_params(2, N, dt=dt, eps=cfg["eps"], storage=cfg["storage"], extrap_states=2)
+        return msc.Solver(p, p0, u0, stream=stream)
+
+    s = solver()
+    s.bdf2_step(2)
+    s.close()
+    s = solver()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = s.bdf2_step(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s.close()
+    s = solver()
+    s.set_recording(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.bdf2_step(nsteps)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    lam = torch.zeros(s.state_size(), dtype=torch.float64, device="cuda")
+    lam[3 * 9 * N * N + N * N:] = 1e-3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.bdf2_adjoint_device(nsteps, lam.data_ptr())
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    s.close()
+    log(f"[bench] adjoint N={N}: forward {t_fwd * 1e3:.2f} ms, with checkpoints {t_rec * 1e3:.2f} ms, "
+        f"backward {t_bwd * 1e3:.2f} ms")
+    return {"N": N, "steps": nsteps, "dt": dt, "storage": cfg["storage"],
+            "mean_inner": float(np.mean([x["iters"] for x in st])), "forward_s": t_fwd,
+            "forward_with_checkpoints_s": t_rec, "backward_s": t_bwd,
+            "backward_over_forward": t_bwd / t_fwd,
+            "note": "backward recomputes each step's inner iterates in FP64 from its checkpoint, then "
+                    "runs the FP64 transposed sweeps and corrections"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +444,7 @@ def main():
             "rand2d_n1024_fp16dev": extra_workload(msc, W, stream, torch, "rand2d_n1024_fp32", "fp16dev",
                                                    ref_cache=cache),
             "tgv3d_n128_fp32": extra_workload(msc, W, stream, torch, "tgv3d_n128_fp32", "fp32"),
+            "adjoint_vort2d_n256_fp32": adjoint_workload(msc, W, stream, torch),
         }
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
