@@ -255,6 +255,63 @@ def adjoint_workload(msc, W, stream, torch):
                     "runs the FP64 transposed sweeps and corrections"}
 
 
+def envelope(msc, W, stream, torch, N=128):
+    """Operating envelope of the corrected iteration (FP64 storage, one interior
+    BDF2 step, eps = 1e-10, 2D Taylor-Green at Re = 1 unless stated):
+    observed contraction rho_obs (Eq. rho-observed) along Lambda at nu = 1/6
+    and along nu at Lambda = 1/4 beside the ghost-survival amplitude
+    eta(nu) = |6 nu - 1| / (6 nu + 1) (Eq. eta), and the (Re, dt) stability
+    cells of the step-size scan (Sec. 4.6)."""
+    def one_step_rho(tau_p, tau_m, nu, dt, Re=1.0, flow="tgv"):
+        U = Re * nu / N
+        p0, u0 = W.tgv2d(N, U, nu) if flow == "tgv" else W.random_field_2d(N, U, seed=1)
+        p = msc.make_params(2, N, dt=dt, eps=1e-10, storage="fp64", tau_plus=tau_p, tau_minus=tau_m,
+                            k_max=2000)
+        s = msc.Solver(p, p0, u0, stream=stream)
+        rc, st = s.bdf2_step(2, raise_on_fail=False)
+        s.close()
+        last = st[-1]
+        return {"status": int(rc), "iters": int(last["iters"]), "rho_obs": last["rho_obs"],
+                "R_first": last["R_first"], "R_final": last["R_final"]}
+
+    out = {"N": N, "dt": 64.0, "lambda_sweep_nu_1_6": [], "nu_sweep_lambda_1_4": [], "stability_re_dt": []}
+    nu0 = 1.0 / 6.0
+    for flow in ("tgv", "random"):
+        for lam in (1 / 64, 1 / 16, 1 / 8, 3 / 16, 1 / 4, 3 / 8, 1 / 2, 1.0, 2.0, 4.0):
+            tau_p = 0.5 + 3 * nu0
+            tau_m = 0.5 + lam / (tau_p - 0.5)
+            r = one_step_rho(tau_p, tau_m, nu0, 64.0, flow=flow)
+            r.update({"flow": flow, "Lambda": lam, "tau_minus": tau_m, "odd_survival": abs(1 - 1 / tau_m)})
+            out["lambda_sweep_nu_1_6"].append(r)
+            log(f"[envelope] {flow} Lambda {lam:.4f}: rho {r['rho_obs']:.3f} iters {r['iters']} status {r['status']}")
+        for nu in (0.05, 0.06, 0.07, 0.08, 0.09, 0.1, 0.12, 0.14, 1 / 6, 0.2, 0.25, 0.35, 0.5):
+            tau_p = 0.5 + 3 * nu
+            tau_m = 0.5 + 1 / (12 * nu)
+            r = one_step_rho(tau_p, tau_m, nu, 64.0, flow=flow)
+            r.update({"flow": flow, "nu": nu, "eta": abs(6 * nu - 1) / (6 * nu + 1)})
+            out["nu_sweep_lambda_1_4"].append(r)
+            log(f"[envelope] {flow} nu {nu:.4f}: eta {r['eta']:.3f} rho {r['rho_obs']:.3f} iters {r['iters']} "
+                f"status {r['status']}")
+    # (Re, dt) cells at N = 128 (the paper's pair S = 32 stable, S = 16
+    # divergent at Re = 100, and its scan at Re = 120, 150, 180)
+    for Re in (100.0, 120.0, 150.0, 180.0):
+        T_end = int(math.floor(0.15 * N * N + 0.5))
+        for S in (128, 32, 16):
+            dt = T_end / S
+            U = Re * nu0 / N
+            p0, u0 = W.tgv2d(N, U, nu0)
+            p = msc.make_params(2, N, dt=dt, eps=1e-10, storage="fp64", k_max=3000)
+            s = msc.Solver(p, p0, u0, stream=stream)
+            rc, st = s.bdf2_step(S, raise_on_fail=False)
+            m = s.moments() if rc == 0 else None
+            s.close()
+            ok = rc == 0 and bool(np.all(np.isfinite(m)))
+            out["stability_re_dt"].append({"Re": Re, "S": S, "dt": dt, "status": int(rc), "stable": ok,
+                                           "mean_inner": float(np.mean([x["iters"] for x in st]))})
+            log(f"[envelope] Re {Re:.0f} dt {dt:.1f}: status {rc}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +328,8 @@ def main():
                     help="skip the N=1024 (FP32, FP16 deviation) and D3Q19 N=128 workloads")
     ap.add_argument("--march-only", action="store_true",
                     help="only the timed corrected march and its sweep timing pass (counter runs)")
+    ap.add_argument("--envelope", action="store_true",
+                    help="only the operating-envelope measurements (rho_obs along Lambda and nu, (Re, dt) cells)")
     ap.add_argument("--calib", action="store_true",
                     help="end with five 64 MiB device copies (a known-size kernel for counter calibration)")
     ap.add_argument("--sweep-only", action="store_true",
@@ -290,6 +349,9 @@ def main():
     if args.sweep_only:
         r = sweep_beyond_cache(msc, stream, torch)
         print(json.dumps({"sweep_beyond_cache": r}), flush=True)
+        return
+    if args.envelope:
+        print(json.dumps({"envelope": envelope(msc, W, stream, torch)}), flush=True)
         return
     cfg = W.config(args.workload)
     N, nu, d = cfg["N"], cfg["nu"], cfg["d"]

@@ -366,3 +366,27 @@ def test_tgv3d_fp32_vs_fp64_oracle(M, orc):
     say("fp32 3d rel velocity error", err)
     assert err <= 1e-5
     s.close()
+
+
+@pytest.mark.parametrize("tau", [(1.0, 1.375), (0.92, 0.5 + 1.0 / (12.0 * 0.14)), (1.25, 0.5 + 1.0 / (12.0 * 0.25))])
+def test_off_design_march_fp64(M, orc, tau):
+    """Off the operating point (Lambda != 1/4 at nu = 1/6; nu != 1/6 on
+    Lambda = 1/4): two BDF steps of the random field at the oracle's inner
+    counts, all fields and the observed contraction against the oracle."""
+    N = 32
+    nu = (tau[0] - 0.5) / 3.0
+    p0, u0 = W.random_field_2d(N, nu / N, seed=5, jmax=6)
+    ref = orc.march(p0, u0, dt=64.0, nsteps=2, eps=1e-10, nmin=2, tau_plus=tau[0], tau_minus=tau[1], kmax=2000)
+    assert ref.status == 0
+    K = [st["iters"] for st in ref.stats]
+    s = _solver(M, (N, N), dt=64.0, eps=1e-10, tau=tau, p0=p0, u0=u0, k_max=2000)
+    s.set_schedule(K)
+    rc, stats = s.bdf2_step(2)
+    assert rc == 0
+    for a, b in zip(stats, ref.stats):
+        assert a["iters"] == b["iters"]
+        if b["rho_obs"] == b["rho_obs"]:
+            assert abs(a["rho_obs"] - b["rho_obs"]) <= 1e-8
+    say("off-design", tau, "K", K, "rho", [x["rho_obs"] for x in stats])
+    assert rel(s.moments(), ref.m) <= 1e-12
+    s.close()
