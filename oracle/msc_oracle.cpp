@@ -26,6 +26,8 @@
 //   history extrapolation and
 //   rotation order ............ Sec. 3.1, last paragraph
 //   contraction factor ........ Eq. (rho-observed)
+//   full-symbol reference ..... Sec. 4.1, Eq. (full-symbol): collision
+//                               Jacobian at rest, per-wavevector Q x Q solve
 //
 // Readings where the paper is silent are listed in the design notes; the ones
 // that matter here: m^0 = P f^0; the extrapolation counts f^0 as an accepted
@@ -360,6 +362,102 @@ void reconstruct(const Lattice& L, const Grid& G, const double* f, const double*
   }
 }
 
+// ------------------------------------------------ full-symbol reference --
+// Sec. 4.1, Eq. (full-symbol): the off-design reference corrector.  It
+// linearises the sweep about the uniform rest state (p, u) = (1, 0) and
+// inverts the linearisation exactly on all Q population fields and every
+// wavevector.
+
+// Collision Jacobian J[i*Q + j] = dC_i/df_j at the rest state f = feq(1, 0)
+// with the case's (omega+, omega-) and dual-time coefficient a, and h = a m
+// there (so that s = 0 and the rest state is a fixed point of the sweep).
+// C is a polynomial of degree two in f (Eq. feq is quadratic in m, Eq.
+// source-distribution is bilinear in (u, s_u), and m, s are affine in f), so
+// a central difference reproduces the derivative up to rounding for any step:
+// step_fd <= 0 takes central differences of unit step.  step_fd > 0 takes the
+// paper's one-sided forward difference of that step (1e-7 in the paper),
+// which adds a truncation error of order step_fd.
+void collision_jacobian(const Lattice& L, double a, double wp, double wm, double step_fd, double* J) {
+  const int Q = L.Q, D = L.d;
+  double mrest[4] = {1.0, 0.0, 0.0, 0.0}, hrest[4] = {0, 0, 0, 0};
+  for (int b = 0; b <= D; ++b) hrest[b] = a * mrest[b];
+  double f0[19], fp[19], fm[19], Cp[19], Cm[19];
+  for (int k = 0; k < Q; ++k) f0[k] = feq_k(L, k, mrest);
+  for (int j = 0; j < Q; ++j) {
+    for (int k = 0; k < Q; ++k) fp[k] = fm[k] = f0[k];
+    double width;
+    if (step_fd > 0.0) {
+      fp[j] += step_fd;
+      width = step_fd;
+    } else {
+      fp[j] += 1.0;
+      fm[j] -= 1.0;
+      width = 2.0;
+    }
+    collide_site(L, fp, hrest, a, wp, wm, Cp, nullptr, nullptr);
+    collide_site(L, fm, hrest, a, wp, wm, Cm, nullptr, nullptr);
+    for (int i = 0; i < Q; ++i) J[i * Q + j] = (Cp[i] - Cm[i]) / width;
+  }
+}
+
+// Solve A x = b (n x n complex, row-major) by Gaussian elimination with
+// partial pivoting; A and b are overwritten, x is returned in b.
+void dense_solve(std::vector<cplx>& A, std::vector<cplx>& b, int n) {
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::abs(A[r * n + col]) > std::abs(A[piv * n + col])) piv = r;
+    if (piv != col) {
+      for (int c = 0; c < n; ++c) std::swap(A[col * n + c], A[piv * n + c]);
+      std::swap(b[col], b[piv]);
+    }
+    for (int r = col + 1; r < n; ++r) {
+      const cplx fac = A[r * n + col] / A[col * n + col];
+      for (int c = col; c < n; ++c) A[r * n + c] -= fac * A[col * n + c];
+      b[r] -= fac * b[col];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    cplx acc = b[r];
+    for (int c = r + 1; c < n; ++c) acc -= A[r * n + c] * b[c];
+    b[r] = acc / A[r * n + r];
+  }
+}
+
+// Eq. (full-symbol): df = F^{-1}[ (I - Z(k) J)^{-1} F[r](k) ] on all Q fields
+// and every wavevector.  Z(k) = diag(exp(-i k . c_q)) is the symbol of push
+// streaming under the forward transform of Eq. (fft-convention):
+// fT_q(x + c_q) = C_q(x) gives F[fT_q](k) = exp(-i k . c_q) F[C_q](k).
+void full_symbol_field(const Lattice& L, const Grid& G, const double* J, const double* r, double* df) {
+  const int Q = L.Q, D = G.d;
+  const int64_t NS = G.NS;
+  std::vector<std::vector<cplx>> rh(Q, std::vector<cplx>(NS));
+  for (int q = 0; q < Q; ++q) {
+    for (int64_t s = 0; s < NS; ++s) rh[q][s] = cplx(r[q * NS + s], 0.0);
+    fft_nd(G, rh[q], -1);
+  }
+  std::vector<cplx> A((size_t)Q * Q), b(Q);
+  for (int64_t s = 0; s < NS; ++s) {
+    int c[3];
+    G.coords(s, c[0], c[1], c[2]);
+    double k[3] = {0, 0, 0};
+    for (int ax = 0; ax < D; ++ax) k[ax] = 2.0 * kPi * signed_index(c[ax], G.n[ax]) / G.n[ax];
+    for (int i = 0; i < Q; ++i) {
+      double kc = 0.0;
+      for (int ax = 0; ax < D; ++ax) kc += k[ax] * L.c[i][ax];
+      const cplx z = std::polar(1.0, -kc);
+      for (int j = 0; j < Q; ++j) A[i * Q + j] = ((i == j) ? 1.0 : 0.0) - z * J[i * Q + j];
+      b[i] = rh[i][s];
+    }
+    dense_solve(A, b, Q);
+    for (int q = 0; q < Q; ++q) rh[q][s] = b[q];
+  }
+  for (int q = 0; q < Q; ++q) {
+    fft_nd(G, rh[q], +1);
+    for (int64_t s = 0; s < NS; ++s) df[q * NS + s] = rh[q][s].real();
+  }
+}
+
 // ------------------------------------------------------------ adjoint --
 // Discrete adjoint (transpose) of the sweep with respect to f and h.  The
 // forward map at a site is M = P f, m = (M + h/2)/(1 + a/2), s = h - a m,
@@ -490,9 +588,12 @@ struct orc_params {
   double eps;       // raw-residual tolerance
   int kmax;         // inner cap
   int nmin;         // minimum accepted inner count
-  int corrector;    // 0 = plain Picard, 1 = periodic shadow correction
+  int corrector;    // 0 = plain Picard, 1 = periodic shadow correction,
+                    // 2 = full-symbol reference (Eq. full-symbol)
   int extrap_states; // 0 = the paper's extrapolation rule; 1, 2, 3 cap it at
                      // constant, linear, cubic (a non-paper option)
+  double fd_step;    // corrector 2: 0 = exact collision Jacobian (central
+                     // differences), > 0 = the paper's forward difference
 };
 
 struct orc_step_stats {
@@ -563,6 +664,42 @@ int orc_corrected_iteration(int d, const int* n, const double* f, const double* 
   sweep(L, G, f, h, a, wp, wm, fT, Pr, R);
   shadow_field(G, Pr, a, nu, dm);
   lift_add(L, G, fT, dm, f_next);
+  return ORC_OK;
+}
+
+// Collision Jacobian at rest (see collision_jacobian): J is Q x Q row-major.
+int orc_collision_jacobian(int d, double a, double wp, double wm, double step_fd, double* J) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  collision_jacobian(L, a, wp, wm, step_fd, J);
+  return ORC_OK;
+}
+
+// Full-symbol correction field df of a residual r (Q x NS) with Jacobian J.
+int orc_full_symbol(int d, const int* n, const double* J, const double* r, double* df) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  full_symbol_field(L, G, J, r, df);
+  return ORC_OK;
+}
+
+// One full-symbol corrected iteration: fT = T(f), r = fT - f, J at rest for
+// (a, omega+, omega-) (exact, step_fd = 0, or forward difference), and
+// f_next = f + df.
+int orc_full_symbol_iteration(int d, const int* n, const double* f, const double* h, double a,
+                              double wp, double wm, double step_fd, double* f_next, double* fT,
+                              double* R) {
+  if (d != 2 && d != 3) return ORC_ERR_INVALID;
+  Lattice L = make_lattice(d);
+  Grid G(d, n);
+  const size_t FQ = (size_t)L.Q * G.NS;
+  std::vector<double> J((size_t)L.Q * L.Q), r(FQ), df(FQ);
+  sweep(L, G, f, h, a, wp, wm, fT, nullptr, R);
+  collision_jacobian(L, a, wp, wm, step_fd, J.data());
+  for (size_t i = 0; i < FQ; ++i) r[i] = fT[i] - f[i];
+  full_symbol_field(L, G, J.data(), r.data(), df.data());
+  for (size_t i = 0; i < FQ; ++i) f_next[i] = f[i] + df[i];
   return ORC_OK;
 }
 
@@ -673,6 +810,11 @@ int orc_march_state(const orc_params* P, double* state, int64_t* bdf_count, int 
       fn2(state + 2 * FQ, state + 3 * FQ), mn(state + 3 * FQ, state + 3 * FQ + FM),
       mn1(state + 3 * FQ + FM, state + 3 * FQ + 2 * FM);
   std::vector<double> f(FQ), fT(FQ), Pr(FM), dm(FM), h(FM), mnew(FM);
+  std::vector<double> Jfs((size_t)Q * Q), rfs, dfs;
+  if (P->corrector == 2) {
+    rfs.resize(FQ);
+    dfs.resize(FQ);
+  }
   std::vector<double> Rl;
   int status = ORC_OK, done = 0;
   int64_t bc = *bdf_count;
@@ -682,6 +824,8 @@ int orc_march_state(const orc_params* P, double* state, int64_t* bdf_count, int 
     const double a = (q == 1) ? 1.0 / P->dt : 3.0 / (2.0 * P->dt);
     for (size_t i = 0; i < FM; ++i)
       h[i] = (q == 1) ? mn[i] / P->dt : (4.0 * mn[i] - mn1[i]) / (2.0 * P->dt);
+    // the full-symbol reference linearises with this step's a
+    if (P->corrector == 2) collision_jacobian(L, a, wp, wm, P->fd_step, Jfs.data());
     // Initial trial by population-history extrapolation (Sec. 3.1).
     const int64_t cap = (P->extrap_states == 0) ? 2 : P->extrap_states - 1;
     const int64_t order = std::min<int64_t>(bc, cap);
@@ -721,6 +865,11 @@ int orc_march_state(const orc_params* P, double* state, int64_t* bdf_count, int 
       if (P->corrector == 1) {
         shadow_field(G, Pr.data(), a, nu, dm.data());
         lift_add(L, G, fT.data(), dm.data(), f.data());
+      } else if (P->corrector == 2) {
+        // Eq. (full-symbol): f <- f + df, (I - Z J) df^ = r^
+        for (size_t i = 0; i < FQ; ++i) rfs[i] = fT[i] - f[i];
+        full_symbol_field(L, G, Jfs.data(), rfs.data(), dfs.data());
+        for (size_t i = 0; i < FQ; ++i) f[i] += dfs[i];
       } else {
         f.swap(fT);
       }
@@ -818,7 +967,7 @@ int orc_shadow_adjoint(int d, const int* n, const double* y, double a, double nu
 int orc_march_adjoint(const orc_params* P, const double* state0, int64_t bdf_count0, int nsteps,
                       const int* schedule, double* lam) {
   const int d = P->d;
-  if ((d != 2 && d != 3) || !schedule) return ORC_ERR_INVALID;
+  if ((d != 2 && d != 3) || !schedule || P->corrector == 2) return ORC_ERR_INVALID;
   Lattice L = make_lattice(d);
   Grid G(d, P->n);
   const int Q = L.Q, D = d;

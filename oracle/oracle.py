@@ -45,6 +45,7 @@ class OrcParams(ctypes.Structure):
         ("nmin", ctypes.c_int),
         ("corrector", ctypes.c_int),
         ("extrap_states", ctypes.c_int),
+        ("fd_step", ctypes.c_double),
     ]
 
 
@@ -95,7 +96,12 @@ def lib():
         L.orc_shadow_adjoint.argtypes = [ctypes.c_int, _ip, _dp, ctypes.c_double, ctypes.c_double, _dp]
         L.orc_march_adjoint.argtypes = [ctypes.POINTER(OrcParams), _dp, ctypes.c_int64, ctypes.c_int, _ip, _dp]
         L.orc_initial_state_adjoint.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp, _dp, _dp]
-        for name in ("orc_sweep_adjoint", "orc_shadow_adjoint", "orc_march_adjoint", "orc_initial_state_adjoint",
+        L.orc_collision_jacobian.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, _dp]
+        L.orc_full_symbol.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp]
+        L.orc_full_symbol_iteration.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+        for name in ("orc_collision_jacobian", "orc_full_symbol", "orc_full_symbol_iteration", "orc_sweep_adjoint", "orc_shadow_adjoint", "orc_march_adjoint", "orc_initial_state_adjoint",
                      "orc_march_state", "orc_initial_state", "orc_lattice", "orc_sweep", "orc_shadow", "orc_corrected_iteration", "orc_fft",
                      "orc_tables", "orc_init_populations", "orc_moments", "orc_explicit",
                      "orc_march"):
@@ -272,9 +278,10 @@ def initial_state(p0, u0):
     return st
 
 
-def _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extrap_states=0):
+def _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extrap_states=0, fd_step=0.0):
     P = OrcParams()
     P.extrap_states = extrap_states
+    P.fd_step = fd_step
     P.d = d
     P.n = (ctypes.c_int * 3)(*(list(shape) + [1] * (3 - len(shape))))
     P.tau_plus, P.tau_minus, P.dt, P.eps = tau_plus, tau_minus, dt, eps
@@ -283,10 +290,10 @@ def _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extra
 
 
 def march_state(state, bdf_count, shape, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1,
-                tau_plus=1.0, tau_minus=1.0, schedule=None, extrap_states=0):
+                tau_plus=1.0, tau_minus=1.0, schedule=None, extrap_states=0, fd_step=0.0):
     """Advance a full march state; returns (status, new_state, bdf_count, stats)."""
     d = len(shape)
-    P = _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extrap_states)
+    P = _params(d, shape, dt, eps, kmax, nmin, corrector, tau_plus, tau_minus, extrap_states, fd_step)
     st = np.array(state, dtype=np.float64, copy=True)
     bc = ctypes.c_int64(int(bdf_count))
     stats = (OrcStepStats * max(nsteps, 1))()
@@ -301,8 +308,11 @@ def march_state(state, bdf_count, shape, *, dt, nsteps, eps=1e-10, kmax=300, nmi
 
 
 def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_plus=1.0,
-          tau_minus=1.0, schedule=None, keep_rhist=False, extrap_states=0) -> MarchResult:
-    """Dual-time march by Algorithm 1 (corrector=1) or Picard (corrector=0)."""
+          tau_minus=1.0, schedule=None, keep_rhist=False, extrap_states=0, fd_step=0.0) -> MarchResult:
+    """Dual-time march by Algorithm 1 (corrector=1), Picard (corrector=0) or
+    with the full-symbol reference corrector of Eq. (full-symbol)
+    (corrector=2; fd_step 0 = exact Jacobian at rest, > 0 = the paper's
+    forward difference of that step)."""
     p0, u0 = _c64(p0), _c64(u0)
     d = u0.shape[0]
     shape = p0.shape
@@ -313,6 +323,7 @@ def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_p
     P.tau_plus, P.tau_minus, P.dt, P.eps = tau_plus, tau_minus, dt, eps
     P.kmax, P.nmin, P.corrector = kmax, nmin, corrector
     P.extrap_states = extrap_states
+    P.fd_step = fd_step
     st = (OrcStepStats * max(nsteps, 1))()
     f = np.zeros((Q,) + shape)
     m = np.zeros((d + 1,) + shape)
@@ -328,6 +339,39 @@ def march(p0, u0, *, dt, nsteps, eps=1e-10, kmax=300, nmin=2, corrector=1, tau_p
                   converged=s.converged) for s in st[: nsteps]]
     return MarchResult(rc, done.value, f, m, stats,
                        Rh.reshape(nsteps, kmax) if Rh is not None else None)
+
+
+# -------------------------------------------------------- full symbol --
+def collision_jacobian(d, a, wp, wm, fd_step=0.0):
+    """Q x Q collision Jacobian dC/df at the rest state (p, u) = (1, 0), h = a m
+    (Sec. 4.1): exact (central differences of the quadratic map) for
+    fd_step <= 0, else the one-sided forward difference of that step."""
+    Q = 9 if d == 2 else 19
+    J = np.zeros((Q, Q))
+    assert lib().orc_collision_jacobian(d, a, wp, wm, fd_step, _p(J)) == 0
+    return J
+
+
+def full_symbol(r, J):
+    """df = F^{-1}[(I - Z(k) J)^{-1} F[r]] on all fields and wavevectors (Eq. full-symbol)."""
+    r = _c64(r)
+    d = r.ndim - 1
+    df = np.zeros_like(r)
+    assert lib().orc_full_symbol(d, _dims(r.shape[1:]), _p(_c64(J)), _p(r), _p(df)) == 0
+    return df
+
+
+def full_symbol_iteration(f, h, a, wp, wm, fd_step=0.0):
+    """One full-symbol corrected iteration: returns (f_next, fT, R)."""
+    f = _c64(f)
+    d = f.ndim - 1
+    hh = _c64(h) if h is not None else None
+    fn = np.zeros_like(f)
+    fT = np.zeros_like(f)
+    R = ctypes.c_double()
+    assert lib().orc_full_symbol_iteration(d, _dims(f.shape[1:]), _p(f), _p(hh) if hh is not None else None, a,
+                                           wp, wm, fd_step, _p(fn), _p(fT), ctypes.byref(R)) == 0
+    return fn, fT, R.value
 
 
 # ------------------------------------------------------------------ adjoint --
