@@ -56,7 +56,16 @@ typedef enum msc_lattice { MSC_D2Q9 = 2, MSC_D3Q19 = 3 } msc_lattice;
 
 typedef enum msc_corrector {
   MSC_CORRECTOR_PICARD = 0, /* plain fixed-point iteration f <- T(f) */
-  MSC_CORRECTOR_SHADOW = 1  /* periodic macroscopic shadow correction (Alg. 1) */
+  MSC_CORRECTOR_SHADOW = 1, /* periodic macroscopic shadow correction (Alg. 1) */
+  /* Off-design reference corrector (Sec. 4.1, Eq. full-symbol): the sweep
+   * linearised about the rest state (p, u) = (1, 0) has the per-wavevector
+   * symbol Z(k) J (Z(k) = diag(exp(-i k.c_q)), J the collision Jacobian at
+   * rest for the case's omega+-, a); each inner iteration solves
+   * [I - Z(k) J] df^ = r^ on all Q fields and every wavevector and sets
+   * f <- f + df, with the raw-residual test of Algorithm 1.  D2Q9 only, FP64
+   * or FP32 storage, extents up to 512 (FP32) / 256 (FP64); J in closed
+   * form (the paper forms it by a forward difference of step 1e-7). */
+  MSC_CORRECTOR_FULL_SYMBOL = 2
 } msc_corrector;
 
 typedef enum msc_storage {
@@ -126,8 +135,9 @@ msc_status msc_params_default(msc_params* p, int32_t lattice, int32_t n, double 
  * NULL pointers); MSC_ERR_OUT_OF_MEMORY; MSC_ERR_DEVICE; MSC_ERR_UNSUPPORTED
  * with the shadow corrector for a grid larger than the transform kernels
  * support (2D: x extent up to 2048 in FP32 and 1024 in FP64, y extent up to
- * 4096 and 2048; 3D: every extent up to 2048 and 1024).  *out is owned by
- * the library until msc_free. */
+ * 4096 and 2048; 3D: every extent up to 2048 and 1024), and with the
+ * full-symbol corrector outside D2Q9, FP64/FP32 storage and extents up to
+ * 512 (FP32) / 256 (FP64).  *out is owned by the library until msc_free. */
 msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, msc_ctx** out);
 
 /* Advance nsteps physical steps by Algorithm 1 (or Picard with
@@ -189,8 +199,10 @@ msc_status msc_sweep(msc_ctx* c, const double* f, const double* h, double a, dou
 
 /* One corrected iteration (Alg. 1 body): fT = T(f), r = fT - f,
  * dm = F^{-1}[chi H^{-1} F[P r]] (Eq. schur, shadow-update) and
- * f_next = fT + E dm (Eq. lift).  Outputs (any may be NULL): f_next, dm
- * ((d+1)*N_sites), R.  Host FP64.  Does not change the march state. */
+ * f_next = fT + E dm (Eq. lift).  With MSC_CORRECTOR_FULL_SYMBOL instead
+ * f_next = f + F^{-1}[(I - Z J)^{-1} F[r]] (Eq. full-symbol) and dm is set
+ * to zero.  Outputs (any may be NULL): f_next, dm ((d+1)*N_sites), R.  Host
+ * FP64.  Does not change the march state. */
 msc_status msc_correct(msc_ctx* c, const double* f, const double* h, double a, double* f_next,
                        double* dm, double* R);
 
@@ -234,7 +246,8 @@ msc_status msc_recorded_steps(const msc_ctx* c, int32_t* count);
  * is FP64, whatever the storage precision.  lam is a device pointer when
  * on_device is nonzero.  MSC_ERR_INVALID_ARG for nsteps outside that range;
  * MSC_ERR_UNSUPPORTED with the shadow corrector where the FP64 transforms do
- * not fit (2D: x extent > 1024 or y extent > 2048; 3D: an extent > 1024).
+ * not fit (2D: x extent > 1024 or y extent > 2048; 3D: an extent > 1024),
+ * and with the full-symbol corrector.
  * The march state is not changed. */
 msc_status msc_bdf2_adjoint(msc_ctx* c, int32_t nsteps, double* lam, int32_t on_device);
 

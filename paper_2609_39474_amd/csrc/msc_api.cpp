@@ -67,7 +67,8 @@ msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, 
   if (!(p->tau_plus > 0.5) || !(p->tau_minus > 0.5) || !(p->dt > 0.0) || !(p->eps > 0.0) ||
       !std::isfinite(p->dt) || p->k_max < 1 || p->n_min < 1)
     return MSC_ERR_INVALID_ARG;
-  if (p->corrector != MSC_CORRECTOR_PICARD && p->corrector != MSC_CORRECTOR_SHADOW)
+  if (p->corrector != MSC_CORRECTOR_PICARD && p->corrector != MSC_CORRECTOR_SHADOW &&
+      p->corrector != MSC_CORRECTOR_FULL_SYMBOL)
     return MSC_ERR_INVALID_ARG;
   if (p->extrap_states < 0 || p->extrap_states > 3) return MSC_ERR_INVALID_ARG;
   if (p->storage != MSC_STORAGE_FP64 && p->storage != MSC_STORAGE_FP32 &&

@@ -13,6 +13,7 @@
 #include <hip/hip_ext.h>
 
 #include "msc_adjoint.h"
+#include "msc_fullsym.h"
 #include "msc_solver.h"
 
 namespace msc {
@@ -155,6 +156,11 @@ class Solver : public SolverBase {
     return guard([&]() -> msc_status {
       if (P.corrector == MSC_CORRECTOR_SHADOW && !corrector_supported()) {
         last_error = "the shadow corrector is not available for this lattice/grid size";
+        return MSC_ERR_UNSUPPORTED;
+      }
+      if (fullsym() && !fs_supported()) {
+        last_error = "the full-symbol corrector needs D2Q9 with FP64 or FP32 storage and its transforms "
+                     "in LDS (N_x, N_y <= 512 FP32 / 256 FP64 per line pass)";
         return MSC_ERR_UNSUPPORTED;
       }
       allocate();
@@ -399,6 +405,7 @@ class Solver : public SolverBase {
 
   msc_status correct(const double* f, const double* h_in, double a, double* fnext, double* dm_out,
                      double* R) override {
+    if (fullsym()) return correct_fullsym(f, h_in, a, fnext, dm_out, R);
     return guard([&]() -> msc_status {
       if (!corrector_supported()) {
         last_error = "the shadow corrector is not available for this lattice/grid";
@@ -427,6 +434,32 @@ class Solver : public SolverBase {
       if (dm_out) download_tm(dm, dm_out, (int64_t)(D + 1) * G.NS);
       sync();
       sig = sig_state;
+      return MSC_OK;
+    });
+  }
+
+  // One full-symbol corrected iteration from host arrays: f_T = T(f), the
+  // correction of Eq. (full-symbol), f_next = f + df; dm_out (no macroscopic
+  // correction field here) is zeroed.
+  msc_status correct_fullsym(const double* f, const double* h_in, double a, double* fnext, double* dm_out,
+                             double* R) {
+    return guard([&]() -> msc_status {
+      pull_ctl();
+      T* A = fb.p[cur_roles().slot_w[0]];
+      T* B = fb.p[cur_roles().slot_w[1]];
+      upload_pop(f, A);
+      upload_h(h_in);
+      SweepArgs<T, TM> S = sweep_args(a);
+      S.src = A;
+      S.dst = B;
+      S.rout = rfs;
+      launch_sweep_timed(SW_DTS, S, 0);
+      const double Rv = reduce_partials(S);
+      if (R) *R = Rv;
+      enqueue_fullsym(nullptr, 0, 0, a, nullptr, nullptr, true, true, B);
+      if (fnext) download_pop(B, fnext);
+      sync();
+      if (dm_out) std::memset(dm_out, 0, sizeof(double) * (D + 1) * G.NS);
       return MSC_OK;
     });
   }
@@ -504,6 +537,10 @@ class Solver : public SolverBase {
       }
       if (P.corrector == MSC_CORRECTOR_SHADOW && !fft_fits(sizeof(cpx<double>))) {
         last_error = "the FP64 transforms of the adjoint correction do not fit this grid size";
+        return MSC_ERR_UNSUPPORTED;
+      }
+      if (fullsym()) {
+        last_error = "the adjoint covers the Picard and shadow correctors only";
         return MSC_ERR_UNSUPPORTED;
       }
       int kmax = 1;
@@ -597,6 +634,8 @@ class Solver : public SolverBase {
   TM* dm = nullptr;
   cpx<CT>* spec = nullptr;
   cpx<CT>* spec2 = nullptr;
+  TM* rfs = nullptr;           // full symbol: residual of every field (Q x NS)
+  cpx<CT>* spec_fs = nullptr;  // full symbol: half spectrum (Q x N_x x (N_y/2 + 1))
   double* partials = nullptr;
   double* partials_h = nullptr;
   double* presum = nullptr;                   // folded partials for large sweep grids
@@ -722,6 +761,14 @@ class Solver : public SolverBase {
 
   bool corrector_supported() const { return fft_fits(); }
 
+  bool fullsym() const { return P.corrector == MSC_CORRECTOR_FULL_SYMBOL; }
+  // the full-symbol passes at their minimum block shape: one row of
+  // (Q+1)/2 packed lines, one column of Q lines, each with its LDS ping-pong
+  bool fs_supported(size_t c = sizeof(cpx<CT>)) const {
+    if (D != 2 || DV) return false;
+    return (size_t)2 * ((Q + 1) / 2) * G.N2 * c <= 131072 && (size_t)2 * Q * G.N0 * c <= 131072;
+  }
+
   // LDS of the transform passes at their minimum block shape
   bool fft_fits(size_t c = sizeof(cpx<CT>)) const {
     if (D == 2) return (size_t)4 * G.N2 * c <= 131072 && (size_t)6 * G.N0 * c <= 131072;
@@ -758,6 +805,13 @@ class Solver : public SolverBase {
         for (int a = 0; a < 3; ++a) tw[a] = make_twiddles(G.n[a]);
       }
       set_fft_attrs();
+    }
+    if (fullsym() && fs_supported()) {
+      rfs = keep((TM*)dalloc(sizeof(TM) * (int64_t)Q * NS));
+      spec_fs = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * (int64_t)Q * G.N0 * (G.N2 / 2 + 1)));
+      if (!tw[0]) tw[0] = make_twiddles(G.N0);
+      if (!tw[2]) tw[2] = make_twiddles(G.N2);
+      set_fs_attrs();
     }
   }
 
@@ -1283,6 +1337,7 @@ class Solver : public SolverBase {
     const double fb1 = (double)pop_bytes(), mb1 = (double)(D + 1) * NS;
     if (mode == SW_EXPLICIT) return 2.0 * fb1;
     double b = 2.0 * fb1 + mb1 * sizeof(TM);  // f in, f_T out, P r out
+    if (fullsym()) b += (double)(Q - D - 1) * NS * sizeof(TM);  // r of every field instead of P r
     if (fuse_rows && (mode == SW_DTS_LIFT || mode == SW_DTS_SETUP))  // row spectrum out instead of P r
       b += (double)(D + 1) * G.N0 * (G.N2 / 4 + 1) * sizeof(cpx<TM>) - mb1 * sizeof(TM);
     if (mode == SW_DTS_SETUP)
@@ -1415,6 +1470,7 @@ class Solver : public SolverBase {
       mode = SW_DTS_SETUP;
     else
       mode = (P.corrector == MSC_CORRECTOR_SHADOW) ? SW_DTS_LIFT : SW_DTS;
+    if (fullsym()) S.rout = rfs;
     if (fuse_rows) {
       S.fuse_rows = 1;
       S.lgr = ilog2(G.N2);
@@ -1435,6 +1491,8 @@ class Solver : public SolverBase {
     if (P.corrector == MSC_CORRECTOR_SHADOW) {
       XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
       enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last, fuse_rows);
+    } else if (fullsym()) {
+      enqueue_fullsym(ctl, n, ell, a, &Ac, &F, true, !last, nullptr);
     } else {
       hipLaunchKernelGGL((k_accept<L, T>), dim3(ew_grid()), dim3(256), 0, st, Ac, F);
       MSC_HIPCK(hipGetLastError());
@@ -1444,6 +1502,10 @@ class Solver : public SolverBase {
   // The correction passes after the first for (step n, sweep ell), guarded on
   // the device (they run only if that sweep was not accepted).
   void enqueue_correction_tail(int n, int ell, double a) {
+    if (fullsym()) {
+      enqueue_fullsym(ctl, n, ell, a, nullptr, nullptr, false, true, nullptr);
+      return;
+    }
     if (P.corrector != MSC_CORRECTOR_SHADOW) return;
     XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
@@ -1527,6 +1589,87 @@ class Solver : public SolverBase {
     }
   }
 
+
+  // Full-symbol launch shapes: rows per block of the row passes (LDS-limited,
+  // >= 128 blocks where the grid allows), j_y columns per block of the
+  // column pass (>= 64 blocks where possible)
+  int fs_rows_per_block() const {
+    const size_t c = sizeof(cpx<CT>);
+    int R = (int)std::max<size_t>(1, (size_t)65536 / (2 * ((Q + 1) / 2) * G.N2 * c));
+    int p = 1;
+    while (p * 2 <= R) p *= 2;
+    while (p > 1 && G.N0 / p < 128) p >>= 1;
+    return std::min(p, G.N0);
+  }
+  int fs_cols_per_block() const {
+    const size_t c = sizeof(cpx<CT>);
+    int J = (int)std::max<size_t>(1, (size_t)98304 / (2 * Q * G.N0 * c));
+    J = std::min(J, 8);
+    const int NH = G.N2 / 2 + 1;
+    while (J > 1 && (NH + J - 1) / J < 64) J >>= 1;
+    return std::max(J, 1);
+  }
+  size_t fs_rows_lds() const { return (size_t)2 * ((Q + 1) / 2) * fs_rows_per_block() * G.N2 * sizeof(cpx<CT>); }
+  size_t fs_cols_lds() const { return (size_t)2 * Q * fs_cols_per_block() * G.N0 * sizeof(cpx<CT>); }
+
+  void set_fs_attrs() {
+    if constexpr (D == 2 && !DV) {
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fs_rows_fwd<L, T, CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)fs_rows_lds()));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fs_rows_inv<L, T, CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)fs_rows_lds()));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fs_cols_solve<L, T, CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)fs_cols_lds()));
+    }
+  }
+
+  // The full-symbol correction of Eq. (full-symbol) for (step n, sweep ell),
+  // guarded on the device like the shadow passes.  head: the rows pass (with
+  // Ac and Fin, it decides acceptance first); tail: the column pass and the
+  // inverse rows pass, which leave f_{l+1} in the sweep's output buffer (out
+  // when c is null).
+  void enqueue_fullsym(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac,
+                       const FinishArgs* Fin, bool head, bool tail, T* out) {
+    if constexpr (D == 2 && !DV) {
+      FsArgs<T, CT, TM> F{};
+      F.g = CorrGuard{c, n, ell};
+      F.do_accept = (Ac && Fin) ? 1 : 0;
+      F.Nx = G.N0;
+      F.Ny = G.N2;
+      F.lgx = ilog2(G.N0);
+      F.lgy = ilog2(G.N2);
+      F.NH = G.N2 / 2 + 1;
+      F.rows_per_block = fs_rows_per_block();
+      F.cols_per_block = fs_cols_per_block();
+      F.r = rfs;
+      F.spec = spec_fs;
+      F.twx = tw[0];
+      F.twy = tw[2];
+      F.a = a;
+      F.wp = wp;
+      F.wm = wm;
+      F.inv_ns = 1.0 / (double)G.NS;
+      F.fb = fb;
+      F.out = out;
+      const int rgrid = G.N0 / F.rows_per_block;
+      if (head) {
+        AcceptArgs<L, T> none{};
+        const FinishArgs nofin{};
+        hipLaunchKernelGGL((k_fs_rows_fwd<L, T, CT, TM>), dim3(rgrid), dim3(256), fs_rows_lds(), st, F,
+                           Ac ? *Ac : none, Fin ? *Fin : nofin);
+        MSC_HIPCK(hipGetLastError());
+      }
+      if (tail) {
+        const int cgrid = (F.NH + F.cols_per_block - 1) / F.cols_per_block;
+        hipLaunchKernelGGL((k_fs_cols_solve<L, T, CT, TM>), dim3(cgrid), dim3(256), fs_cols_lds(), st, F);
+        MSC_HIPCK(hipGetLastError());
+        hipLaunchKernelGGL((k_fs_rows_inv<L, T, CT, TM>), dim3(rgrid), dim3(256), fs_rows_lds(), st, F);
+        MSC_HIPCK(hipGetLastError());
+      }
+    } else {
+      (void)c, (void)n, (void)ell, (void)a, (void)Ac, (void)Fin, (void)head, (void)tail, (void)out;
+    }
+  }
 
   // The shadow correction of Eq. (shadow-update) for (step n, sweep ell):
   // transforms of P r, per-wavevector Schur solve, inverse transforms into dm

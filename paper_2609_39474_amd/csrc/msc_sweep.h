@@ -180,6 +180,8 @@ struct SweepArgs {
   double* h;        // (d+1) x NS FP64 history term h_q: read, or written in setup mode
   const TM* dm;     // (d+1) x NS, previous shadow correction
   TM* Pr;           // (d+1) x NS, residual moments out
+  TM* rout;         // Q x NS, the raw residual of every field out instead of
+                    // P r (full-symbol correction), or null
   double* partials; // one FP64 partial sum of r^2 per block
   double a, inv1pa2;  // a_q and 1/(1 + a_q/2)
   double wp, wm;      // omega+, omega-
@@ -655,6 +657,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
           if constexpr (!PopDev<T>::value) __builtin_nontemporal_store((T)v, &dst[k * NS + site]);
           if (MODE != SW_EXPLICIT) {
             const CT r = v - fprev[j][k];
+            if (A.rout) __builtin_nontemporal_store((TM)r, &A.rout[k * NS + site]);
             pr[0] += r;
 #pragma unroll
             for (int bb = 0; bb < D; ++bb)
@@ -667,7 +670,7 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
             // the row of P r (fields 0 and 1 packed in one complex line, field 2 in a second)
             fbuf[i2] = {pr[0], pr[1]};
             fbuf[T2 + i2] = {pr[2], (CT)0};
-          } else {
+          } else if (!A.rout) {
 #pragma unroll
             for (int bb = 0; bb <= D; ++bb) __builtin_nontemporal_store((TM)pr[bb], &A.Pr[bb * NS + site]);
           }

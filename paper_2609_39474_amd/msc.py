@@ -33,6 +33,7 @@ MSC_D2Q9 = 2
 MSC_D3Q19 = 3
 MSC_CORRECTOR_PICARD = 0
 MSC_CORRECTOR_SHADOW = 1
+MSC_CORRECTOR_FULL_SYMBOL = 2
 MSC_STORAGE_FP64 = 0
 MSC_STORAGE_FP32 = 1
 MSC_STORAGE_FP16_DEV = 2
@@ -370,7 +371,8 @@ def make_params(d, N, *, dt, eps, storage="fp64", corrector="shadow", tau_plus=1
                 k_max=300, n_min=None, extrap_states=0):
     p = msc_params_default(MSC_D2Q9 if d == 2 else MSC_D3Q19, N, dt, eps)
     p.storage = {"fp64": MSC_STORAGE_FP64, "fp32": MSC_STORAGE_FP32, "fp16dev": MSC_STORAGE_FP16_DEV}[storage]
-    p.corrector = {"shadow": MSC_CORRECTOR_SHADOW, "picard": MSC_CORRECTOR_PICARD}[corrector]
+    p.corrector = {"shadow": MSC_CORRECTOR_SHADOW, "picard": MSC_CORRECTOR_PICARD,
+                   "full_symbol": MSC_CORRECTOR_FULL_SYMBOL}[corrector]
     p.tau_plus = tau_plus
     p.tau_minus = tau_minus
     p.k_max = k_max
