@@ -262,11 +262,11 @@ def envelope(msc, W, stream, torch, N=128):
     and along nu at Lambda = 1/4 beside the ghost-survival amplitude
     eta(nu) = |6 nu - 1| / (6 nu + 1) (Eq. eta), and the (Re, dt) stability
     cells of the step-size scan (Sec. 4.6)."""
-    def one_step_rho(tau_p, tau_m, nu, dt, Re=1.0, flow="tgv"):
+    def one_step_rho(tau_p, tau_m, nu, dt, Re=1.0, flow="tgv", corrector="shadow"):
         U = Re * nu / N
         p0, u0 = W.tgv2d(N, U, nu) if flow == "tgv" else W.random_field_2d(N, U, seed=1)
         p = msc.make_params(2, N, dt=dt, eps=1e-10, storage="fp64", tau_plus=tau_p, tau_minus=tau_m,
-                            k_max=2000)
+                            k_max=2000, corrector=corrector)
         s = msc.Solver(p, p0, u0, stream=stream)
         rc, st = s.bdf2_step(2, raise_on_fail=False)
         s.close()
@@ -282,16 +282,20 @@ def envelope(msc, W, stream, torch, N=128):
             tau_m = 0.5 + lam / (tau_p - 0.5)
             r = one_step_rho(tau_p, tau_m, nu0, 64.0, flow=flow)
             r.update({"flow": flow, "Lambda": lam, "tau_minus": tau_m, "odd_survival": abs(1 - 1 / tau_m)})
+            r["full_symbol"] = one_step_rho(tau_p, tau_m, nu0, 64.0, flow=flow, corrector="full_symbol")
             out["lambda_sweep_nu_1_6"].append(r)
-            log(f"[envelope] {flow} Lambda {lam:.4f}: rho {r['rho_obs']:.3f} iters {r['iters']} status {r['status']}")
+            log(f"[envelope] {flow} Lambda {lam:.4f}: rho {r['rho_obs']:.3f} iters {r['iters']} status {r['status']}; "
+                f"full symbol rho {r['full_symbol']['rho_obs']:.2e} iters {r['full_symbol']['iters']}")
         for nu in (0.05, 0.06, 0.07, 0.08, 0.09, 0.1, 0.12, 0.14, 1 / 6, 0.2, 0.25, 0.35, 0.5):
             tau_p = 0.5 + 3 * nu
             tau_m = 0.5 + 1 / (12 * nu)
             r = one_step_rho(tau_p, tau_m, nu, 64.0, flow=flow)
             r.update({"flow": flow, "nu": nu, "eta": abs(6 * nu - 1) / (6 * nu + 1)})
+            r["full_symbol"] = one_step_rho(tau_p, tau_m, nu, 64.0, flow=flow, corrector="full_symbol")
             out["nu_sweep_lambda_1_4"].append(r)
             log(f"[envelope] {flow} nu {nu:.4f}: eta {r['eta']:.3f} rho {r['rho_obs']:.3f} iters {r['iters']} "
-                f"status {r['status']}")
+                f"status {r['status']}; full symbol rho {r['full_symbol']['rho_obs']:.2e} "
+                f"iters {r['full_symbol']['iters']}")
     # (Re, dt) cells at N = 128 (the paper's pair S = 32 stable, S = 16
     # divergent at Re = 100, and its scan at Re = 120, 150, 180)
     for Re in (100.0, 120.0, 150.0, 180.0):
@@ -312,6 +316,58 @@ def envelope(msc, W, stream, torch, N=128):
     return out
 
 
+def fullsym_cost(msc, W, stream, torch, sizes=((256, "fp32"), (256, "fp64"), (128, "fp64"))):
+    """Cost of one inner iteration with the full-symbol reference corrector
+    (Eq. full-symbol: every population field, every wavevector) beside the
+    shadow correction (three fields, band-pruned), D2Q9 random field at the
+    operating point, dt = 64: 4 timed BDF2 steps of 8 replayed iterations
+    each after 2 untimed steps; plus the inner counts and seconds per step of
+    both correctors run to eps = 1e-10 (FP64) at an off-design point
+    (Lambda = 1/64 at nu = 1/6) and at nu = 0.1 on Lambda = 1/4."""
+    out = []
+    nu0 = 1.0 / 6.0
+    for N, storage in sizes:
+        p0, u0 = W.random_field_2d(N, nu0 / N, seed=1)
+        row = {"N": N, "storage": storage}
+        for corr in ("shadow", "full_symbol"):
+            p = msc.make_params(2, N, dt=64.0, eps=1e-30, storage=storage, corrector=corr)
+            s = msc.Solver(p, p0, u0, stream=stream)
+            s.set_schedule([8] * 6)
+            s.bdf2_step(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.bdf2_step(4)
+            torch.cuda.synchronize()
+            row[f"{corr}_us_per_iteration"] = (time.perf_counter() - t0) / 32 * 1e6
+            s.close()
+        row["cost_ratio"] = row["full_symbol_us_per_iteration"] / row["shadow_us_per_iteration"]
+        log(f"[bench] full symbol N={N} {storage}: {row['full_symbol_us_per_iteration']:.1f} us/iteration, "
+            f"shadow {row['shadow_us_per_iteration']:.1f} (x{row['cost_ratio']:.2f})")
+        out.append(row)
+    off = []
+    N = 128
+    for label, tp, tm in (("Lambda=1/64 nu=1/6", 1.0, 0.5 + (1 / 64) / 0.5),
+                          ("nu=0.1 Lambda=1/4", 0.5 + 0.3, 0.5 + 1 / 1.2)):
+        nu = (tp - 0.5) / 3.0
+        p0, u0 = W.random_field_2d(N, nu / N, seed=1)
+        row = {"point": label, "N": N, "tau_plus": tp, "tau_minus": tm}
+        for corr in ("shadow", "full_symbol"):
+            p = msc.make_params(2, N, dt=64.0, eps=1e-10, storage="fp64", corrector=corr, tau_plus=tp,
+                                tau_minus=tm, k_max=2000)
+            s = msc.Solver(p, p0, u0, stream=stream)
+            s.bdf2_step(1, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = s.bdf2_step(1, raise_on_fail=False)
+            torch.cuda.synchronize()
+            row[corr] = {"status": int(rc), "iters": int(st[-1]["iters"]), "rho_obs": st[-1]["rho_obs"],
+                         "seconds_per_step": time.perf_counter() - t0}
+            s.close()
+        log(f"[bench] off-design {label}: shadow {row['shadow']}, full symbol {row['full_symbol']}")
+        off.append(row)
+    return {"per_iteration": out, "off_design_step": off}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +386,8 @@ def main():
                     help="only the timed corrected march and its sweep timing pass (counter runs)")
     ap.add_argument("--envelope", action="store_true",
                     help="only the operating-envelope measurements (rho_obs along Lambda and nu, (Re, dt) cells)")
+    ap.add_argument("--fullsym", action="store_true",
+                    help="only the full-symbol reference corrector: cost per iteration and off-design steps")
     ap.add_argument("--calib", action="store_true",
                     help="end with five 64 MiB device copies (a known-size kernel for counter calibration)")
     ap.add_argument("--sweep-only", action="store_true",
@@ -352,6 +410,9 @@ def main():
         return
     if args.envelope:
         print(json.dumps({"envelope": envelope(msc, W, stream, torch)}), flush=True)
+        return
+    if args.fullsym:
+        print(json.dumps({"full_symbol": fullsym_cost(msc, W, stream, torch)}), flush=True)
         return
     cfg = W.config(args.workload)
     N, nu, d = cfg["N"], cfg["nu"], cfg["d"]
@@ -508,6 +569,7 @@ def main():
             "tgv3d_n128_fp32": extra_workload(msc, W, stream, torch, "tgv3d_n128_fp32", "fp32"),
             "adjoint_vort2d_n256_fp32": adjoint_workload(msc, W, stream, torch),
         }
+        out["full_symbol_reference"] = fullsym_cost(msc, W, stream, torch)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:

@@ -56,35 +56,57 @@ struct FsArgs {
 };
 
 // Eq. (full-symbol) at one wavevector, FP64: y holds r^ on entry and
-// df^ = (I - Z J)^{-1} r^ on return.
+// df^ = (I - Z J)^{-1} r^ on return.  kpi[b] = k_b / pi = 2 j_b / N_b (signed
+// index j_b), so that exp(-i k_b) comes from sincospi without a large-argument
+// reduction and the Q phase factors z_q = exp(-i k . c_q) are products of the
+// d axis factors (c_q components are -1, 0, 1).
 template <class L>
-__device__ inline void fs_solve(const double* kv, double (*y)[2], double a, double wp, double wm) {
+__device__ inline void fs_solve(const double* kpi, double (*y)[2], double a, double wp, double wm) {
   constexpr int Q = L::Q, D = L::D, D1 = D + 1;
   const double bp = 1.0 - wp, bm = 1.0 - wm;
   const double beta = 0.5 * (bp + bm), gam = 0.5 * (bp - bm);
   const double cpl = (wp - a * (1.0 - 0.5 * wp)) / (1.0 + 0.5 * a);
   const double cmi = (wm - a * (1.0 - 0.5 * wm)) / (1.0 + 0.5 * a);
+  double er[D], ei[D];  // exp(-i k_b)
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    double sn, cs;
+    sincospi(kpi[b], &sn, &cs);
+    er[b] = cs;
+    ei[b] = -sn;
+  }
   double zr[Q], zi[Q];  // z_q = exp(-i k . c_q)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    double th = 0.0;
+    double pr = 1.0, pi = 0.0;
 #pragma unroll
-    for (int b = 0; b < D; ++b) th += kv[b] * (double)ca<L>(q, b);
-    double s, c;
-    sincos(th, &s, &c);
-    zr[q] = c;
-    zi[q] = -s;
+    for (int b = 0; b < D; ++b) {
+      const int cb = ca<L>(q, b);
+      if (cb == 0) continue;
+      const double fr = er[b], fi = (cb > 0) ? ei[b] : -ei[b];
+      const double tr = pr * fr - pi * fi;
+      pi = pr * fi + pi * fr;
+      pr = tr;
+    }
+    zr[q] = pr;
+    zi[q] = pi;
   }
+  // 1/det of each opposite pair's 2 x 2 block of A (indexed by the pair's
+  // lower direction)
+  double invd[Q];
+#pragma unroll
+  for (int q = 1; q < Q; ++q)
+    invd[q] = (L::opp(q) > q) ? 1.0 / (1.0 - 2.0 * beta * zr[q] + beta * beta - gam * gam) : 0.0;
+  const double iwp = 1.0 / wp;
   // v <- A^{-1} v in place (A = I - Z B)
   auto apply_Ainv = [&](double (*v)[2]) {
-    v[0][0] /= wp;  // rest direction: 1 - b+ = w+
-    v[0][1] /= wp;
+    v[0][0] *= iwp;  // rest direction: 1 - b+ = w+
+    v[0][1] *= iwp;
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
       const int p = L::opp(q);
       if (p < q) continue;
-      const double det = 1.0 - 2.0 * beta * zr[q] + beta * beta - gam * gam;
-      const double id = 1.0 / det;
+      const double id = invd[q];
       // [[1 - conj(z) beta, z gam], [conj(z) gam, 1 - z beta]] / det
       const double ar = 1.0 - beta * zr[q], ai = beta * zi[q];   // 1 - conj(z) beta
       const double br = gam * zr[q], bi = gam * zi[q];           // z gam
@@ -303,12 +325,11 @@ __global__ __launch_bounds__(256) void k_fs_cols_solve(FsArgs<T, CT, TM> A) {
   __syncthreads();
   cpx<CT>* F = lds_fft<CT>(buf, tmp, A.lgx, Q * JB, -1, A.twx);
   cpx<CT>* G = (F == buf) ? tmp : buf;
-  const double two_pi = 6.283185307179586476925286766559;
   for (int i = threadIdx.x; i < JB * Nx; i += blockDim.x) {
     const int c = i / Nx, jx = i - c * Nx;
     const int jy = j0 + c;
     if (jy < NH) {
-      const double kv[2] = {two_pi * signed_index(jx, Nx) / Nx, two_pi * jy / A.Ny};
+      const double kpi[2] = {2.0 * signed_index(jx, Nx) / Nx, 2.0 * jy / A.Ny};
       double v[Q][2];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
@@ -316,7 +337,7 @@ __global__ __launch_bounds__(256) void k_fs_cols_solve(FsArgs<T, CT, TM> A) {
         v[q][0] = (double)z.x;
         v[q][1] = (double)z.y;
       }
-      fs_solve<L>(kv, v, A.a, A.wp, A.wm);
+      fs_solve<L>(kpi, v, A.a, A.wp, A.wm);
       // df^ - r^ (r^ read again from LDS), with the 1/N_sites of the inverse
 #pragma unroll
       for (int q = 0; q < Q; ++q) {

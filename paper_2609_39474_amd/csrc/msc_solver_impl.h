@@ -1591,14 +1591,15 @@ class Solver : public SolverBase {
 
 
   // Full-symbol launch shapes: rows per block of the row passes (LDS-limited,
-  // >= 128 blocks where the grid allows), j_y columns per block of the
-  // column pass (>= 64 blocks where possible)
+  // >= 512 blocks where the grid allows), j_y columns per block of the
+  // column pass (>= 256 blocks where possible).  At N <= 512 every pass is
+  // latency-bound, so these keep one row / one column per block there.
   int fs_rows_per_block() const {
     const size_t c = sizeof(cpx<CT>);
     int R = (int)std::max<size_t>(1, (size_t)65536 / (2 * ((Q + 1) / 2) * G.N2 * c));
     int p = 1;
     while (p * 2 <= R) p *= 2;
-    while (p > 1 && G.N0 / p < 128) p >>= 1;
+    while (p > 1 && G.N0 / p < 512) p >>= 1;
     return std::min(p, G.N0);
   }
   int fs_cols_per_block() const {
@@ -1606,7 +1607,7 @@ class Solver : public SolverBase {
     int J = (int)std::max<size_t>(1, (size_t)98304 / (2 * Q * G.N0 * c));
     J = std::min(J, 8);
     const int NH = G.N2 / 2 + 1;
-    while (J > 1 && (NH + J - 1) / J < 64) J >>= 1;
+    while (J > 1 && (NH + J - 1) / J < 256) J >>= 1;
     return std::max(J, 1);
   }
   size_t fs_rows_lds() const { return (size_t)2 * ((Q + 1) / 2) * fs_rows_per_block() * G.N2 * sizeof(cpx<CT>); }
