@@ -276,10 +276,12 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
  * enqueued beyond the previous step's count (>= 0, default 0), 4 = capture
  * explicit-march chunks in HIP graphs (0/1, default 1), 5 = sweep tile by
  * its 1-based position in the library's tile table (0 = automatic; overrides
- * key 0), 6 = in 2D, do the forward row transform of the correction inside
- * the sweep when a tile spans whole rows (0/1, default 1).  Results do not
- * depend on these beyond rounding order.  MSC_ERR_INVALID_ARG for an unknown
- * key. */
+ * key 0), 6 = in 2D with tiles spanning whole rows, do the correction's row
+ * transforms inside the sweep: 0 = neither, 1 = the forward one, 2 = the
+ * forward one and, with one-plane strips, the inverse one before the lift
+ * (default 2).  Results do not depend on these beyond rounding order (keys 6
+ * = 1 and 2 give identical results).  MSC_ERR_INVALID_ARG for an unknown key
+ * or value. */
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);
 
 #ifdef __cplusplus

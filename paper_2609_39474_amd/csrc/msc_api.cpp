@@ -281,7 +281,10 @@ msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
     case 3: t.spec_extra = value < 0 ? 0 : value; break;
     case 4: t.use_graph = value != 0; break;
     case 5: t.sweep_tile_index = value < 0 ? 0 : value; break;
-    case 6: t.fuse_rows = value != 0; break;
+    case 6:
+      if (value < 0 || value > 2) return MSC_ERR_INVALID_ARG;
+      t.fuse_rows = value;
+      break;
     default: return MSC_ERR_INVALID_ARG;
   }
   if (key <= 1 || key >= 5) return fwd(c, c->s->reconfigure());

@@ -30,7 +30,8 @@ struct Tuning {
   int batch_steps = 32;   // physical steps enqueued between host synchronisations
   int spec_extra = 0;     // speculative iterations beyond the last step's count
   int use_graph = 1;      // capture explicit chunks in hipGraphs
-  int fuse_rows = 1;      // 2D: forward row transform inside the sweep where tiles span rows
+  int fuse_rows = 2;      // 2D, tiles spanning rows: 1 = forward row transform inside the sweep,
+                          // 2 = also the inverse row transform (one-plane strips)
   int sweep_tile_index = 0;  // 1-based entry of the tile table, 0 = automatic
 };
 

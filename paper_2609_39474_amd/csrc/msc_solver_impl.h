@@ -78,8 +78,12 @@ void launch_sweep_tile(int mode, const SweepArgs<T, TM>& A, int grid, hipStream_
     launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS>(A, grid, st, ev0, ev1);
   else if (mode == SW_DTS_LIFT)
     launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_LIFT>(A, grid, st, ev0, ev1);
-  else
+  else if (mode == SW_DTS_SETUP)
     launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_SETUP>(A, grid, st, ev0, ev1);
+  else if constexpr (T1 == 1 && NT == T2 && L::D == 2)
+    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_LIFT_ROWS>(A, grid, st, ev0, ev1);
+  else
+    throw DeviceError{hipErrorInvalidValue, "inverse-row lift requested for a tile that does not span rows"};
 }
 
 
@@ -634,6 +638,7 @@ class Solver : public SolverBase {
   TM* dm = nullptr;
   cpx<CT>* spec = nullptr;
   cpx<CT>* spec2 = nullptr;
+  cpx<CT>* spec_alt = nullptr;  // 2D: second band spectrum (inverse rows in the sweep)
   TM* rfs = nullptr;           // full symbol: residual of every field (Q x NS)
   cpx<CT>* spec_fs = nullptr;  // full symbol: half spectrum (Q x N_x x (N_y/2 + 1))
   double* partials = nullptr;
@@ -796,6 +801,7 @@ class Solver : public SolverBase {
       if (D == 2) {
         const int NB = G.N2 / 4 + 1;
         spec = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * 3 * (int64_t)G.N0 * NB));
+        spec_alt = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * 3 * (int64_t)G.N0 * NB));
         tw[0] = make_twiddles(G.N0);
         tw[2] = make_twiddles(G.N2);
       } else {
@@ -1242,6 +1248,9 @@ class Solver : public SolverBase {
   // 2D with the shadow corrector and tiles spanning whole rows: the sweep
   // also does the forward row transform of P r
   bool fuse_rows = false;
+  // ... and the inverse row transform before the lift (one-plane strips): the
+  // correction's spectrum then alternates between spec and spec_alt
+  bool fuse_inv = false;
 
   void choose_sweep() {
     const int n = TileSet<L>::count;
@@ -1296,6 +1305,7 @@ class Solver : public SolverBase {
     strip_L = std::max(Lp, 1);
     fuse_rows = D == 2 && P.corrector == MSC_CORRECTOR_SHADOW && tile.T1 == 1 && tile.T2 == G.N2 &&
                 tile.NT == tile.T2 && corrector_supported() && tune.fuse_rows != 0;
+    fuse_inv = fuse_rows && strip_L == 1 && tune.fuse_rows >= 2;
   }
 
   int sweep_grid() const {
@@ -1338,13 +1348,15 @@ class Solver : public SolverBase {
     if (mode == SW_EXPLICIT) return 2.0 * fb1;
     double b = 2.0 * fb1 + mb1 * sizeof(TM);  // f in, f_T out, P r out
     if (fullsym()) b += (double)(Q - D - 1) * NS * sizeof(TM);  // r of every field instead of P r
-    if (fuse_rows && (mode == SW_DTS_LIFT || mode == SW_DTS_SETUP))  // row spectrum out instead of P r
+    if (fuse_rows && (lift_mode(mode) || mode == SW_DTS_SETUP))  // row spectrum out instead of P r
       b += (double)(D + 1) * G.N0 * (G.N2 / 4 + 1) * sizeof(cpx<TM>) - mb1 * sizeof(TM);
     if (mode == SW_DTS_SETUP)
       b += order * fb1 + mb1 * sizeof(double) * (q == 2 ? 3.0 : 2.0);
     else
       b += mb1 * sizeof(double);
     if (mode == SW_DTS_LIFT) b += mb1 * sizeof(TM);
+    if (mode == SW_DTS_LIFT_ROWS)  // the band spectrum rows in instead of dm
+      b += (double)(D + 1) * G.N0 * (G.N2 / 4 + 1) * sizeof(cpx<TM>);
     return b;
   }
 
@@ -1468,15 +1480,18 @@ class Solver : public SolverBase {
     int mode;
     if (ell == 1)
       mode = SW_DTS_SETUP;
+    else if (P.corrector == MSC_CORRECTOR_SHADOW)
+      mode = fuse_inv ? SW_DTS_LIFT_ROWS : SW_DTS_LIFT;
     else
-      mode = (P.corrector == MSC_CORRECTOR_SHADOW) ? SW_DTS_LIFT : SW_DTS;
+      mode = SW_DTS;
     if (fullsym()) S.rout = rfs;
     if (fuse_rows) {
       S.fuse_rows = 1;
       S.lgr = ilog2(G.N2);
       S.NBr = G.N2 / 4 + 1;
-      S.spec = spec;
+      S.spec = spec_of(ell);
       S.twr = tw[2];
+      if (mode == SW_DTS_LIFT_ROWS) S.spec_in = spec_of(ell - 1);
     }
     launch_sweep_timed(mode, S, 0);
     if (F.nparts > kFusedParts) {
@@ -1489,8 +1504,8 @@ class Solver : public SolverBase {
 
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
     if (P.corrector == MSC_CORRECTOR_SHADOW) {
-      XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
-      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last, fuse_rows);
+      XformBufs<CT, TM> B{Pr, dm, spec_of(ell), spec2, {tw[0], tw[1], tw[2]}};
+      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last && !fuse_inv, fuse_rows);
     } else if (fullsym()) {
       enqueue_fullsym(ctl, n, ell, a, &Ac, &F, true, !last, nullptr);
     } else {
@@ -1507,10 +1522,16 @@ class Solver : public SolverBase {
       return;
     }
     if (P.corrector != MSC_CORRECTOR_SHADOW) return;
-    XformBufs<CT, TM> B{Pr, dm, spec, spec2, {tw[0], tw[1], tw[2]}};
+    if (fuse_inv) return;  // the next sweep inverts the rows itself
+    XformBufs<CT, TM> B{Pr, dm, spec_of(ell), spec2, {tw[0], tw[1], tw[2]}};
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
     enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, nullptr, false, true, fuse_rows);
   }
+
+  // band spectrum of the correction after sweep ell (alternating buffers
+  // when the sweep inverts the previous correction's rows while writing its
+  // own forward rows)
+  cpx<CT>* spec_of(int ell) const { return (fuse_inv && (ell & 1)) ? spec_alt : spec; }
 
   AcceptArgs<L, T> accept_args(int n, int ell, double a) {
     AcceptArgs<L, T> Ac{};

@@ -32,7 +32,12 @@ namespace msc {
 // trial; the same with the previous correction's lift fused into the load;
 // and the first sweep of a physical step, which also forms the BDF history
 // term h_q (Eq. bdf2) and the extrapolated trial (Sec. 3.1) while loading.
-enum { SW_EXPLICIT = 0, SW_DTS = 1, SW_DTS_LIFT = 2, SW_DTS_SETUP = 3 };
+enum { SW_EXPLICIT = 0, SW_DTS = 1, SW_DTS_LIFT = 2, SW_DTS_SETUP = 3, SW_DTS_LIFT_ROWS = 4 };
+// SW_DTS_LIFT_ROWS: the lift mode with the correction's inverse row transform
+// done by the sweep itself (2D, tiles spanning whole rows, one-plane strips):
+// each block inverts the band spectrum rows of its source planes in LDS
+// instead of reading dm.
+__host__ __device__ constexpr bool lift_mode(int m) { return m == SW_DTS_LIFT || m == SW_DTS_LIFT_ROWS; }
 
 template <class T>
 struct CompT;
@@ -199,6 +204,9 @@ struct SweepArgs {
   int fuse_rows, lgr, NBr;
   cpx<TM>* spec;
   const cpx<TM>* twr;
+  // SW_DTS_LIFT_ROWS: the solved band spectrum of the previous correction
+  // ([field][x][j <= N_y/4]), inverted along y by the sweep to give dm
+  const cpx<TM>* spec_in;
 };
 
 // ---- compile-time direction classification -----------------------------
@@ -264,7 +272,7 @@ struct RawSite {
   float M0[DV ? D1 : 1];  // stored moments of each deviation buffer
   float M1[DV && MODE == SW_DTS_SETUP ? D1 : 1];
   float M2[DV && MODE == SW_DTS_SETUP ? D1 : 1];
-  TM dmv[MODE == SW_DTS_LIFT ? D1 : 1];
+  TM dmv[lift_mode(MODE) ? D1 : 1];
   double hv[MODE == SW_EXPLICIT ? 1 : D1];  // h, or m^n in setup mode
   double mpv[MODE == SW_DTS_SETUP ? D1 : 1];
 };
@@ -312,6 +320,7 @@ __device__ __forceinline__ void load_raw(const SweepArgs<T, TM>& A, const SrcPtr
 #pragma unroll
     for (int b = 0; b <= D; ++b) r.dmv[b] = A.dm[b * NS + site];
   }
+  // SW_DTS_LIFT_ROWS: dmv is filled by the caller from the inverted rows
 }
 
 // From the raw loads: the trial populations (extrapolated in setup mode, with
@@ -369,7 +378,7 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
       for (int b = 0; b <= D; ++b) h[b] = r.hv[b];
     }
   }
-  if (MODE == SW_DTS_LIFT) {
+  if (lift_mode(MODE)) {
     const CT d0 = (CT)r.dmv[0];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -391,7 +400,7 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
                                               : (CT)3 * r.M0[b] - (CT)3 * r.M1[b] + r.M2[b]);
       else
         M[b] = r.M0[b];
-      if constexpr (MODE == SW_DTS_LIFT) M[b] += (CT)r.dmv[b];
+      if constexpr (lift_mode(MODE)) M[b] += (CT)r.dmv[b];
     }
   } else {
 #pragma unroll
@@ -469,7 +478,12 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
   // for deviation storage (they are full populations there)
   using LT = typename std::conditional<PopDev<T>::value, float, T>::type;
   constexpr bool ROWFFT = (T1 == 1 && MODE != SW_EXPLICIT && NT == T2);
+  constexpr bool ROWINV = (MODE == SW_DTS_LIFT_ROWS);
+  static_assert(!ROWINV || (ROWFFT && L::D == 2), "inverse rows need 2D tiles spanning whole rows");
   __shared__ cpx<CT> fbuf[ROWFFT ? 4 * T2 : 1];
+  // inverted dm rows of the three source planes of a one-plane strip: line
+  // 2p packs (dm_0 + i dm_1) of plane p, line 2p+1 holds dm_2; ping-pong
+  __shared__ cpx<CT> ibuf[ROWINV ? 12 * T2 : 1];
   __shared__ LT ldsP[4][NGP][NI];
   __shared__ LT ldsZ[3][NG0][NI];
   __shared__ LT ldsM[2][NGM][NI];
@@ -526,6 +540,50 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
       load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs0 * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
     }
   }
+  // SW_DTS_LIFT_ROWS: inverse transform along y of the band spectrum rows of
+  // the source planes x0-1, x0, x0+1 (Eq. fft-convention, the 1/N_Omega is in
+  // the spectrum): the conjugate-symmetric extension of each field's half
+  // band, fields 0 and 1 packed in one complex line, field 2 in a second;
+  // the same arithmetic as the separate inverse row pass
+  const cpx<CT>* dmr = nullptr;
+  if constexpr (ROWINV) {
+    const int NB = A.NBr;
+    const int64_t FS = (int64_t)N0 * NB;
+    for (int i = tid; i < 3 * T2; i += NT) {
+      const int p = i / T2, jj = i - p * T2;
+      const int64_t o = (int64_t)wrapi(x0 - 1 + p, N0) * NB;
+      cpx<CT> a0 = {0, 0}, a1 = {0, 0}, a2 = {0, 0};
+      if (jj < NB) {
+        a0 = A.spec_in[o + jj];
+        a1 = A.spec_in[FS + o + jj];
+        a2 = A.spec_in[2 * FS + o + jj];
+        if (jj == 0) {
+          a0.y = 0;
+          a1.y = 0;
+          a2.y = 0;
+        }
+      } else if (T2 - jj < NB) {
+        const int jm = T2 - jj;
+        a0 = A.spec_in[o + jm];
+        a1 = A.spec_in[FS + o + jm];
+        a2 = A.spec_in[2 * FS + o + jm];
+        a0.y = -a0.y;
+        a1.y = -a1.y;
+        a2.y = -a2.y;
+      }
+      ibuf[(2 * p) * T2 + jj] = {a0.x - a1.y, a0.y + a1.x};
+      ibuf[(2 * p + 1) * T2 + jj] = a2;
+    }
+    __syncthreads();
+    dmr = lds_fft<CT>(ibuf, ibuf + 6 * T2, A.lgr, 6, +1, A.twr);
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+      const int i2 = tid + j * NT;
+      raw[j].dmv[0] = (TM)dmr[i2].x;
+      raw[j].dmv[1] = (TM)dmr[i2].y;
+      raw[j].dmv[2] = (TM)dmr[T2 + i2].x;
+    }
+  }
 
   for (int it = 0; it < A.L + 2; ++it) {
     const int xs = wrapi(x0 - 1 + it, N0);
@@ -543,6 +601,12 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
       if (it + 1 < A.L + 2) {
         const int xn = wrapi(x0 + it, N0);
         load_raw<L, T, TM, MODE>(A, P, ((int64_t)xn * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
+        if constexpr (ROWINV) {
+          const cpx<CT>* row = dmr + 2 * (it + 1) * T2;
+          raw[j].dmv[0] = (TM)row[i2].x;
+          raw[j].dmv[1] = (TM)row[i2].y;
+          raw[j].dmv[2] = (TM)row[T2 + i2].x;
+        }
       }
       CT C[Q];
       double hs[4];

@@ -1,9 +1,10 @@
 """GPU parity of the launch-shape variants (through the C ABI, FP64 storage,
-against the FP64 oracle at 1e-12): the forward row transform fused into the
-sweep or run as its own pass, sweep tiles and strip lengths other than the
-automatic choice, the folded-partials path of large sweep grids, and every
-D3Q19 tile of the library's table.  Results must not depend on these choices
-beyond rounding order.
+against the FP64 oracle at 1e-12): the row transforms of the correction fused
+into the sweep (forward only, or forward and inverse) or run as their own
+passes, sweep tiles and strip lengths other than the automatic choice, the
+folded-partials path of large sweep grids, and every D3Q19 tile of the
+library's table.  Results must not depend on these choices beyond rounding
+order; the two fused variants run the same arithmetic and agree bit for bit.
 """
 import sys
 
@@ -43,7 +44,7 @@ def _solver(M, shape, p0, u0, *, dt, eps=1e-10, n_min=2):
     return M.Solver(p, p0, u0)
 
 
-@pytest.mark.parametrize("fuse", [0, 1])
+@pytest.mark.parametrize("fuse", [0, 1, 2])
 def test_fused_row_transform_on_off(M, orc, fuse):
     """2D TGV N = 64: twelve steps at the oracle's inner counts."""
     cfg = W.config("tgv2d_n64_fp64")
@@ -60,6 +61,27 @@ def test_fused_row_transform_on_off(M, orc, fuse):
     say("fuse_rows", fuse, "rel", e)
     assert e <= 1e-12
     s.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16dev"])
+def test_inverse_rows_in_sweep_bit_exact(M, storage):
+    """The random-field workload at N = 256 (dt = 256, eps = 1e-8, six free
+    running steps): inverse row transform inside the sweep (key 6 = 2) and as
+    its own pass (key 6 = 1) give identical counts and identical moments."""
+    N = 256
+    p0, u0 = W.random_field_2d(N, NU / N, seed=1)
+    out = {}
+    for fuse in (1, 2):
+        p = M.make_params(2, N, dt=256.0, eps=1e-8, storage=storage, extrap_states=2)
+        s = M.Solver(p, p0, u0)
+        s.set_tuning(KEY_FUSE_ROWS, fuse)
+        rc, stats = s.bdf2_step(6)
+        assert rc == 0
+        out[fuse] = ([x["iters"] for x in stats], s.moments())
+        s.close()
+    say(storage, "inverse rows in the sweep: counts", out[2][0], "separate:", out[1][0])
+    assert out[1][0] == out[2][0]
+    assert np.array_equal(out[1][1], out[2][1])
 
 
 SHAPES_2D = [
