@@ -581,7 +581,8 @@ def main():
         nsamp = 0
         t0 = time.perf_counter()
         while nsamp < 2 or (time.perf_counter() - t0 < 12.0 and nsamp < K):
-            rc_, st_, bc_, sst = orc.march_state(st_, bc_, shape, dt=dt, nsteps=1, eps=args.eps, nmin=cfg["nmin"])
+            rc_, st_, bc_, sst = orc.march_state(st_, bc_, shape, dt=dt, nsteps=1, eps=args.eps, nmin=cfg["nmin"],
+                                                 extrap_states=args.extrap)
             its.append(sst[0]["iters"])
             nsamp += 1
         t_cpu = time.perf_counter() - t0
