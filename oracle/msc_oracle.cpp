@@ -574,6 +574,82 @@ void shadow_adjoint_field(const Grid& G, const double* y, double a, double nu, d
 
 bool is_fin(double v) { return std::isfinite(v); }
 
+// ------------------------------------------------ wall-bounded cavity --
+// Sec. 3.3 (boundary-consistent kinetic correction): the D2Q9 lid-driven
+// cavity sweep T_{q,h,Gamma} collides at every node, streams with the modulo
+// wrap of the periodic sweep, then overwrites the wall rows of the streamed
+// array in the order of Eq. (bounceback-rows): y = 0, y = N_y - 1 (moving
+// lid, +x), x = 0, x = N_x - 1.  Each assignment copies the current value of
+// another direction at the same node, so later walls own the corners.
+void cavity_walls(const Grid& G, double ulid, double* fT) {
+  const int64_t NS = G.NS;
+  const int Nx = G.n[0], Ny = G.n[1];
+  auto F = [&](int k, int x, int y) -> double& { return fT[k * NS + G.site(x, y, 0)]; };
+  for (int x = 0; x < Nx; ++x) {  // y = 0
+    F(2, x, 0) = F(4, x, 0);
+    F(5, x, 0) = F(7, x, 0);
+    F(6, x, 0) = F(8, x, 0);
+  }
+  for (int x = 0; x < Nx; ++x) {  // y = N_y - 1, lid
+    F(4, x, Ny - 1) = F(2, x, Ny - 1);
+    F(7, x, Ny - 1) = F(5, x, Ny - 1) - ulid / 6.0;
+    F(8, x, Ny - 1) = F(6, x, Ny - 1) + ulid / 6.0;
+  }
+  for (int y = 0; y < Ny; ++y) {  // x = 0
+    F(1, 0, y) = F(3, 0, y);
+    F(5, 0, y) = F(7, 0, y);
+    F(8, 0, y) = F(6, 0, y);
+  }
+  for (int y = 0; y < Ny; ++y) {  // x = N_x - 1
+    F(3, Nx - 1, y) = F(1, Nx - 1, y);
+    F(6, Nx - 1, y) = F(8, Nx - 1, y);
+    F(7, Nx - 1, y) = F(5, Nx - 1, y);
+  }
+}
+
+// The cavity sweep and its raw residual (Eq. residual) after the wall rows.
+void sweep_cavity(const Lattice& L, const Grid& G, const double* f, const double* h, double a, double wp,
+                  double wm, double ulid, double* fT, double* R) {
+  sweep(L, G, f, h, a, wp, wm, fT, nullptr, nullptr);
+  cavity_walls(G, ulid, fT);
+  if (R) {
+    const int64_t n = (int64_t)L.Q * G.NS;
+    std::vector<double> r2(n);
+    for (int64_t i = 0; i < n; ++i) r2[i] = (fT[i] - f[i]) * (fT[i] - f[i]);
+    *R = std::sqrt(pairwise_sum(r2.data(), n) / (double)n);
+  }
+}
+
+// Eq. (wall-G) and Eq. (wall-local-jacobian) at omega+ = omega- = 1: the
+// derivative of C_k(m; h) = feq_k(m) + Phi_k(m, h - a m)/2 with respect to
+// m at the reference (mref, sref), then J_kk' = (G_k0 + sum_a G_ka c_k'a) /
+// (1 + a/2).  Jc is Q x Q row-major (outgoing k, incoming k').
+void cavity_local_jacobian(const Lattice& L, double a, const double* mref, const double* sref, double* Jc) {
+  const int Q = L.Q, D = L.d;
+  const double cs4 = cs2 * cs2;
+  for (int k = 0; k < Q; ++k) {
+    double G[4];
+    double cu = 0.0;
+    for (int al = 0; al < D; ++al) cu += L.c[k][al] * mref[1 + al];
+    G[0] = L.w[k] * (1.0 - a / 2.0);
+    for (int be = 0; be < D; ++be) {
+      const double ckb = L.c[k][be], ub = mref[1 + be];
+      double g = L.w[k] * (ckb / cs2 + cu * ckb / cs4 - ub / cs2);
+      double src = 0.0;
+      for (int al = 0; al < D; ++al)
+        src += (-(al == be ? 1.0 : 0.0) / cs2 + L.c[k][al] * ckb / cs4) * sref[1 + al];
+      src -= a * ((ckb - ub) / cs2 + cu * ckb / cs4);
+      g += 0.5 * L.w[k] * src;
+      G[1 + be] = g;
+    }
+    for (int kp = 0; kp < Q; ++kp) {
+      double v = G[0];
+      for (int al = 0; al < D; ++al) v += G[1 + al] * L.c[kp][al];
+      Jc[k * Q + kp] = v / (1.0 + a / 2.0);
+    }
+  }
+}
+
 }  // namespace
 
 // =============================================================== C ABI ====
@@ -700,6 +776,32 @@ int orc_full_symbol_iteration(int d, const int* n, const double* f, const double
   for (size_t i = 0; i < FQ; ++i) r[i] = fT[i] - f[i];
   full_symbol_field(L, G, J.data(), r.data(), df.data());
   for (size_t i = 0; i < FQ; ++i) f_next[i] = f[i] + df[i];
+  return ORC_OK;
+}
+
+// D2Q9 lid-driven cavity sweep (walls in the order of Eq. bounceback-rows)
+// with its raw residual.  h may be NULL.
+int orc_sweep_cavity(const int* n, const double* f, const double* h, double a, double wp, double wm,
+                     double ulid, double* fT, double* R) {
+  Lattice L = make_lattice(2);
+  int nn[3] = {n[0], n[1], 1};
+  Grid G(2, nn);
+  sweep_cavity(L, G, f, h, a, wp, wm, ulid, fT, R);
+  return ORC_OK;
+}
+
+// Local collision Jacobians of Eq. (wall-local-jacobian) at every site of a
+// reference field: mref, sref are (d+1) x NS; Jc is NS x Q x Q.
+int orc_cavity_local_jacobians(int64_t NS, double a, const double* mref, const double* sref, double* Jc) {
+  Lattice L = make_lattice(2);
+  for (int64_t s = 0; s < NS; ++s) {
+    double m[3], sv[3];
+    for (int b = 0; b < 3; ++b) {
+      m[b] = mref[b * NS + s];
+      sv[b] = sref[b * NS + s];
+    }
+    cavity_local_jacobian(L, a, m, sv, Jc + s * 81);
+  }
   return ORC_OK;
 }
 

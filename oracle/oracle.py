@@ -96,12 +96,15 @@ def lib():
         L.orc_shadow_adjoint.argtypes = [ctypes.c_int, _ip, _dp, ctypes.c_double, ctypes.c_double, _dp]
         L.orc_march_adjoint.argtypes = [ctypes.POINTER(OrcParams), _dp, ctypes.c_int64, ctypes.c_int, _ip, _dp]
         L.orc_initial_state_adjoint.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp, _dp, _dp]
+        L.orc_sweep_cavity.argtypes = [_ip, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _dp, _dp]
+        L.orc_cavity_local_jacobians.argtypes = [ctypes.c_int64, ctypes.c_double, _dp, _dp, _dp]
         L.orc_collision_jacobian.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, _dp]
         L.orc_full_symbol.argtypes = [ctypes.c_int, _ip, _dp, _dp, _dp]
         L.orc_full_symbol_iteration.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_double, ctypes.c_double,
                                                 ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
-        for name in ("orc_collision_jacobian", "orc_full_symbol", "orc_full_symbol_iteration", "orc_sweep_adjoint", "orc_shadow_adjoint", "orc_march_adjoint", "orc_initial_state_adjoint",
+        for name in ("orc_sweep_cavity", "orc_cavity_local_jacobians", "orc_collision_jacobian", "orc_full_symbol", "orc_full_symbol_iteration", "orc_sweep_adjoint", "orc_shadow_adjoint", "orc_march_adjoint", "orc_initial_state_adjoint",
                      "orc_march_state", "orc_initial_state", "orc_lattice", "orc_sweep", "orc_shadow", "orc_corrected_iteration", "orc_fft",
                      "orc_tables", "orc_init_populations", "orc_moments", "orc_explicit",
                      "orc_march"):
@@ -372,6 +375,173 @@ def full_symbol_iteration(f, h, a, wp, wm, fd_step=0.0):
     assert lib().orc_full_symbol_iteration(d, _dims(f.shape[1:]), _p(f), _p(hh) if hh is not None else None, a,
                                            wp, wm, fd_step, _p(fn), _p(fT), ctypes.byref(R)) == 0
     return fn, fT, R.value
+
+
+# ---------------------------------------------------- wall-bounded cavity --
+# Sec. 3.3 and Algorithm 2: D2Q9 lid-driven cavity, boundary-node modified
+# bounce-back rows of Eq. (bounceback-rows) in the printed order (y = 0,
+# y = N_y - 1 with the moving lid along +x, x = 0, x = N_x - 1), and the
+# kinetic correction (I - L) df = r with L = B_Gamma S blkdiag(J^C(x)) of
+# Eq. (wall-global-jacobian), factorised by a sparse LU (the paper uses a
+# sparse direct solver; scipy's SuperLU here).
+_CAV_WALLS = (
+    ("y0", ((2, 4), (5, 7), (6, 8))),
+    ("y1", ((4, 2), (7, 5), (8, 6))),
+    ("x0", ((1, 3), (5, 7), (8, 6))),
+    ("x1", ((3, 1), (6, 8), (7, 5))),
+)
+
+
+def cavity_sweep(f, h, a, ulid, wp=1.0, wm=1.0):
+    """(f_T, R) of the cavity sweep T_{q,h,Gamma} (h None means h = 0)."""
+    f = _c64(f)
+    fT = np.zeros_like(f)
+    R = ctypes.c_double()
+    hh = _c64(h) if h is not None else None
+    assert lib().orc_sweep_cavity(_dims(f.shape[1:]), _p(f), _p(hh) if hh is not None else None, a, wp, wm,
+                                  ulid, _p(fT), ctypes.byref(R)) == 0
+    return fT, R.value
+
+
+def cavity_local_jacobians(mref, sref, a):
+    """J^C(x) of Eq. (wall-local-jacobian) at every site: (N_sites, Q, Q)."""
+    mref, sref = _c64(mref), _c64(sref)
+    NS = int(np.prod(mref.shape[1:]))
+    Jc = np.zeros((NS, 9, 9))
+    assert lib().orc_cavity_local_jacobians(NS, a, _p(mref), _p(sref), _p(Jc)) == 0
+    return Jc
+
+
+def cavity_row_sources(shape):
+    """lab[k, x, y]: the streamed direction whose row ends in row (k, x, y)
+    after the wall assignments, in their order (copies of copies follow)."""
+    Nx, Ny = shape
+    lab = np.broadcast_to(np.arange(9).reshape(9, 1, 1), (9, Nx, Ny)).copy()
+    for wall, pairs in _CAV_WALLS:
+        sl = {"y0": (slice(None), 0), "y1": (slice(None), Ny - 1), "x0": (0, slice(None)),
+              "x1": (Nx - 1, slice(None))}[wall]
+        for kR, kS in pairs:
+            lab[(kR,) + sl] = lab[(kS,) + sl]
+    return lab
+
+
+def cavity_operator(Jc, shape):
+    """Sparse L = B_Gamma S blkdiag(J^C) (Eq. wall-stream-row, the row copies
+    of Eq. bounceback-rows, Eq. wall-global-jacobian), rows and columns in
+    the canonical order iota(k, x, y) = (k N_x + x) N_y + y."""
+    import scipy.sparse as sp
+    Nx, Ny = shape
+    NS = Nx * Ny
+    c, _, _ = lattice(2)
+    lab = cavity_row_sources(shape).reshape(9, NS)
+    X, Y = np.meshgrid(np.arange(Nx), np.arange(Ny), indexing="ij")
+    X, Y = X.ravel(), Y.ravel()
+    rows, cols, vals = [], [], []
+    for k in range(9):
+        src = lab[k]
+        xu = (X - c[src, 0]) % Nx  # upwind site of the streamed source row
+        yu = (Y - c[src, 1]) % Ny
+        su = xu * Ny + yu
+        for kp in range(9):
+            rows.append(k * NS + np.arange(NS))
+            cols.append(kp * NS + su)
+            vals.append(Jc[su, src, kp])
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(9 * NS, 9 * NS))
+
+
+def _reconstruct(f, h, a):
+    m = moments(f)
+    return (m + (h if h is not None else 0.0) / 2.0) / (1.0 + a / 2.0)
+
+
+def cavity_march(p0, u0, *, ulid, dt, nsteps, eps, kmax=300, nmin=1, corrector="frozen", n_forced=0,
+                 max_refresh=3, schedule=None, extrap_states=0):
+    """Algorithm 2 (corrector "frozen" or "adaptive"), or the Picard
+    iteration with the same walls (corrector "picard"), from f^0 = feq(p0, u0).
+    Returns dict(status, f, m, stats) with per-step q, iters, R list,
+    refresh count and the inner indices at which the operator was refreshed."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    p0, u0 = _c64(p0), _c64(u0)
+    shape = p0.shape
+    NS = int(np.prod(shape))
+    n = 9 * NS
+    f0 = init_populations(p0, u0)
+    fn = f0.copy(); fn1 = f0.copy(); fn2 = f0.copy()
+    mn = moments(f0); mn1 = mn.copy()
+    bc = 0
+    eye = sp.identity(n, format="csc")
+
+    def factor(a_A, mref, sref):
+        Jc = cavity_local_jacobians(mref, sref, a_A)
+        return spl.splu((eye - cavity_operator(Jc, shape)).tocsc())
+
+    lu = None
+    if corrector != "picard":
+        # Algorithm 2: the initial operator at rest (p = 1, u = 0, h_2 = a_2 m,
+        # s = 0), assembled with q_A = 2
+        a2 = 3.0 / (2.0 * dt)
+        mref = np.zeros((3,) + shape); mref[0] = 1.0
+        lu = factor(a2, mref, np.zeros((3,) + shape))
+    stats = []
+    status = 0
+    for step in range(nsteps):
+        q = 1 if bc == 0 else 2
+        a = 1.0 / dt if q == 1 else 3.0 / (2.0 * dt)
+        h = mn / dt if q == 1 else (4.0 * mn - mn1) / (2.0 * dt)
+        cap = 2 if extrap_states == 0 else extrap_states - 1
+        order = min(bc, cap)
+        f = fn.copy() if order == 0 else (2 * fn - fn1 if order == 1 else 3 * fn - 3 * fn1 + fn2)
+        Rl, refreshed = [], []
+        n_grow, n_ref, Rref = 0, 0, None
+        accepted = False
+        for ell in range(1, kmax + 1):
+            fT, R = cavity_sweep(f, h, a, ulid)
+            Rl.append(R)
+            if ell == 1:
+                Rref = R
+            ok = (ell == schedule[step]) if schedule is not None else (ell >= nmin and np.isfinite(R) and R < eps)
+            if ok:
+                mnew = _reconstruct(fT, h, a)
+                fn2, fn1, fn = fn1, fn, fT
+                mn1, mn = mn, mnew
+                accepted = True
+                break
+            if not np.isfinite(R):
+                status = 6
+                break
+            if ell == kmax:
+                break
+            n_grow = n_grow + 1 if (ell > 1 and R > Rl[-2]) else 0
+            if corrector == "adaptive" and n_ref < max_refresh:
+                if n_grow >= 2 or R > 10.0 * Rref or (n_forced > 0 and ell % n_forced == 0):
+                    mref = _reconstruct(f, h, a)  # the current iterate, unchanged histories
+                    lu = factor(a, mref, h - a * mref)
+                    n_ref += 1
+                    n_grow = 0
+                    Rref = R
+                    refreshed.append(ell)
+            r = fT - f
+            if corrector == "picard":
+                f = fT
+            else:
+                f = f + lu.solve(r.ravel()).reshape(f.shape)
+        stats.append(dict(q=q, iters=len(Rl), R=Rl, refreshes=len(refreshed), refreshed_at=refreshed,
+                          converged=accepted))
+        if not accepted:
+            status = status or 5
+            break
+        bc += 1
+    return dict(status=status, f=fn, m=mn, stats=stats)
+
+
+def cavity_explicit(f, nsteps, ulid, wp=1.0, wm=1.0):
+    """Explicit TRT march with the cavity walls (a = 0, h = 0)."""
+    f = _c64(f).copy()
+    for _ in range(int(nsteps)):
+        f, _ = cavity_sweep(f, None, 0.0, ulid, wp, wm)
+    return f
 
 
 # ------------------------------------------------------------------ adjoint --
