@@ -65,8 +65,36 @@ typedef enum msc_corrector {
    * f <- f + df, with the raw-residual test of Algorithm 1.  D2Q9 only, FP64
    * or FP32 storage, extents up to 512 (FP32) / 256 (FP64); J in closed
    * form (the paper forms it by a forward difference of step 1e-7). */
-  MSC_CORRECTOR_FULL_SYMBOL = 2
+  MSC_CORRECTOR_FULL_SYMBOL = 2,
+  /* Wall-bounded kinetic correction (Sec. 3.3, Algorithm 2) for
+   * MSC_BOUNDARY_CAVITY: each inner iteration solves (I - L) df = r with
+   * L = B_Gamma S blkdiag(J^C(x)) (Eq. wall-global-jacobian; J^C of Eq.
+   * wall-local-jacobian at a reference field) and sets f <- f + df.  The
+   * operator is frozen at rest (p = 1, u = 0, s = 0, assembled with the BDF2
+   * coefficient) or, with MSC_WALL_ADAPTIVE, re-linearised at the current
+   * iterate under the residual guard of Algorithm 2.  The library solves the
+   * system by restarted GMRES preconditioned with the periodic full-symbol
+   * inverse at rest (the paper factors it with a sparse direct solver), to
+   * the relative residual krylov_tol.  D2Q9, omega+ = omega- = 1 (Eq.
+   * wall-G holds there), FP64 storage, extents up to 256. */
+  MSC_CORRECTOR_WALL_KINETIC = 3
 } msc_corrector;
+
+typedef enum msc_boundary {
+  MSC_BOUNDARY_PERIODIC = 0, /* every axis periodic (the Fourier correctors) */
+  /* D2Q9 lid-driven cavity (Sec. 3.3): after streaming (with the periodic
+   * wrap) the wall rows of Eq. (bounceback-rows) are overwritten in the
+   * printed order y = 0, y = N_y - 1 (the lid, moving along +x at u_lid),
+   * x = 0, x = N_x - 1, so the side walls own the corners.  Correctors:
+   * MSC_CORRECTOR_PICARD or MSC_CORRECTOR_WALL_KINETIC; the explicit march
+   * and the diagnostic sweep apply the same rows. */
+  MSC_BOUNDARY_CAVITY = 1
+} msc_boundary;
+
+typedef enum msc_wall_operator {
+  MSC_WALL_FROZEN = 0,  /* Algorithm 2, frozen branch: the initial operator for the whole run */
+  MSC_WALL_ADAPTIVE = 1 /* Algorithm 2, adaptive branch: residual-guarded refresh (<= 3 per step) */
+} msc_wall_operator;
 
 typedef enum msc_storage {
   MSC_STORAGE_FP64 = 0, /* FP64 populations, FP64 arithmetic */
@@ -105,6 +133,12 @@ typedef struct msc_params {
   void* (*alloc_fn)(size_t bytes, void* user);
   void (*free_fn)(void* ptr, void* user);
   void* alloc_user;
+  int32_t boundary;      /* msc_boundary (default MSC_BOUNDARY_PERIODIC) */
+  int32_t wall_operator; /* msc_wall_operator (MSC_CORRECTOR_WALL_KINETIC) */
+  double u_lid;          /* lid velocity along +x (MSC_BOUNDARY_CAVITY) */
+  int32_t wall_forced;   /* Algorithm 2's forced refresh interval N_forced, 0 = off (the paper's setting) */
+  int32_t wall_restart;  /* GMRES restart length of the wall corrector, 0 = 50 */
+  double krylov_tol;     /* relative residual of the wall corrector's solve, 0 = 1e-12 */
 } msc_params;
 
 /* Per physical step record (Alg. 1; Eq. rho-observed for rho_obs). */
@@ -115,7 +149,7 @@ typedef struct msc_step_stats {
   double R_final;    /* raw residual RMS of the last sweep */
   double rho_obs;    /* tail geometric-mean contraction, NaN if fewer than 3 residuals */
   int32_t converged; /* 1 if accepted */
-  int32_t reserved;
+  int32_t refreshes; /* Algorithm 2: operator refreshes in this step (wall-kinetic corrector), else 0 */
 } msc_step_stats;
 
 typedef struct msc_ctx msc_ctx;
@@ -266,6 +300,14 @@ msc_status msc_init_adjoint(msc_ctx* c, const double* phat0, const double* u0, c
  * dual-time launches counted separately: kind 0 = dual-time sweep, 1 =
  * explicit sweep).  Enabling resets the counters. */
 msc_status msc_set_kernel_timing(msc_ctx* c, int32_t enable);
+
+/* Counters of the wall corrector's linear solves since msc_init (Sec. 3.3):
+ * solves = corrected inner iterations, iters = GMRES iterations over them,
+ * refreshes = operator re-linearisations (adaptive branch); worst_rel = the
+ * largest final relative residual ||(I - L) df - r|| / ||r|| reached.  Any
+ * output may be NULL.  Zero for the other correctors. */
+msc_status msc_krylov_stats(msc_ctx* c, int64_t* solves, int64_t* iters, int64_t* refreshes,
+                            double* worst_rel);
 msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* launches,
                            double* bytes_per_launch);
 

@@ -53,6 +53,8 @@ msc_status msc_params_default(msc_params* p, int32_t lattice, int32_t n, double 
   p->n_min = (lattice == MSC_D2Q9) ? 2 : 1;
   p->corrector = MSC_CORRECTOR_SHADOW;
   p->storage = MSC_STORAGE_FP64;
+  p->boundary = MSC_BOUNDARY_PERIODIC;
+  p->wall_operator = MSC_WALL_FROZEN;
   return MSC_OK;
 }
 
@@ -68,8 +70,19 @@ msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, 
       !std::isfinite(p->dt) || p->k_max < 1 || p->n_min < 1)
     return MSC_ERR_INVALID_ARG;
   if (p->corrector != MSC_CORRECTOR_PICARD && p->corrector != MSC_CORRECTOR_SHADOW &&
-      p->corrector != MSC_CORRECTOR_FULL_SYMBOL)
+      p->corrector != MSC_CORRECTOR_FULL_SYMBOL && p->corrector != MSC_CORRECTOR_WALL_KINETIC)
     return MSC_ERR_INVALID_ARG;
+  if (p->boundary != MSC_BOUNDARY_PERIODIC && p->boundary != MSC_BOUNDARY_CAVITY) return MSC_ERR_INVALID_ARG;
+  if (p->boundary == MSC_BOUNDARY_CAVITY) {
+    // the cavity of Sec. 3.3 is D2Q9; the Fourier correctors need periodic axes
+    if (d != 2 || !std::isfinite(p->u_lid)) return MSC_ERR_INVALID_ARG;
+    if (p->corrector != MSC_CORRECTOR_PICARD && p->corrector != MSC_CORRECTOR_WALL_KINETIC)
+      return MSC_ERR_INVALID_ARG;
+  } else if (p->corrector == MSC_CORRECTOR_WALL_KINETIC) {
+    return MSC_ERR_INVALID_ARG;
+  }
+  if (p->wall_operator != MSC_WALL_FROZEN && p->wall_operator != MSC_WALL_ADAPTIVE) return MSC_ERR_INVALID_ARG;
+  if (p->wall_forced < 0 || p->wall_restart < 0 || !(p->krylov_tol >= 0.0)) return MSC_ERR_INVALID_ARG;
   if (p->extrap_states < 0 || p->extrap_states > 3) return MSC_ERR_INVALID_ARG;
   if (p->storage != MSC_STORAGE_FP64 && p->storage != MSC_STORAGE_FP32 &&
       p->storage != MSC_STORAGE_FP16_DEV)
@@ -257,6 +270,13 @@ msc_status msc_set_kernel_timing(msc_ctx* c, int32_t enable) {
   if (!c) return MSC_ERR_INVALID_ARG;
   if (c->s->broken) return MSC_ERR_STATE;
   return fwd(c, c->s->set_kernel_timing(enable));
+}
+
+msc_status msc_krylov_stats(msc_ctx* c, int64_t* solves, int64_t* iters, int64_t* refreshes,
+                            double* worst_rel) {
+  if (!c) return MSC_ERR_INVALID_ARG;
+  c->s->krylov_stats(solves, iters, refreshes, worst_rel);
+  return MSC_OK;
 }
 
 msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* launches,

@@ -113,6 +113,37 @@ struct DevCtl {
   Roles roles[2];
 };
 
+// D2Q9 lid-driven cavity (Sec. 3.3, Eq. bounceback-rows): the wall rows of
+// the streamed values v of node (x, y), overwritten in the printed order
+// y = 0, y = N_y - 1 (lid moving along +x at ulid), x = 0, x = N_x - 1; each
+// copies the current value of another direction of the same node, so the
+// side walls own the corners.  With ulid = 0 it is the row replacement of the
+// linearised map (the lid constants have no derivative).
+template <class CT>
+__device__ __forceinline__ void cavity_rows(CT* v, int x, int y, int Nx, int Ny, CT ulid) {
+  const CT u6 = ulid / (CT)6;
+  if (y == 0) {
+    v[2] = v[4];
+    v[5] = v[7];
+    v[6] = v[8];
+  }
+  if (y == Ny - 1) {
+    v[4] = v[2];
+    v[7] = v[5] - u6;
+    v[8] = v[6] + u6;
+  }
+  if (x == 0) {
+    v[1] = v[3];
+    v[5] = v[7];
+    v[8] = v[6];
+  }
+  if (x == Nx - 1) {
+    v[3] = v[1];
+    v[6] = v[8];
+    v[7] = v[5];
+  }
+}
+
 // Population buffers (five, roles assigned through DevCtl slots).
 template <class T>
 struct FBufs {

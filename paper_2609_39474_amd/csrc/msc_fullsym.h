@@ -53,6 +53,9 @@ struct FsArgs {
   double a, wp, wm, inv_ns;
   FBufs<T> fb;             // population buffers (output through the roles) ...
   T* out;                  // ... or this buffer when g.ctl is null
+  // plain solve: out = F^{-1}[(I - Z J)^{-1} F[r]] itself (the column pass
+  // keeps df^, the inverse rows overwrite out), e.g. as a preconditioner
+  int plain;
 };
 
 // Eq. (full-symbol) at one wavevector, FP64: y holds r^ on entry and
@@ -338,12 +341,13 @@ __global__ __launch_bounds__(256) void k_fs_cols_solve(FsArgs<T, CT, TM> A) {
         v[q][1] = (double)z.y;
       }
       fs_solve<L>(kpi, v, A.a, A.wp, A.wm);
-      // df^ - r^ (r^ read again from LDS), with the 1/N_sites of the inverse
+      // df^ - r^ (r^ read again from LDS), or df^ for a plain solve, with
+      // the 1/N_sites of the inverse
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const cpx<CT> z = F[(q * JB + c) * Nx + jx];
-        G[(q * JB + c) * Nx + jx] = {(CT)((v[q][0] - (double)z.x) * A.inv_ns),
-                                     (CT)((v[q][1] - (double)z.y) * A.inv_ns)};
+        const double sr = A.plain ? 0.0 : (double)z.x, si = A.plain ? 0.0 : (double)z.y;
+        G[(q * JB + c) * Nx + jx] = {(CT)((v[q][0] - sr) * A.inv_ns), (CT)((v[q][1] - si) * A.inv_ns)};
       }
     } else {
 #pragma unroll
@@ -407,10 +411,10 @@ __global__ __launch_bounds__(256) void k_fs_rows_inv(FsArgs<T, CT, TM> A) {
     for (int p = 0; p < NL; ++p) {
       const cpx<CT> z = out[(NL * rr + p) * Ny + y];
       const int64_t ia = (2 * p) * NS + s;
-      dst[ia] = (T)((CT)dst[ia] + z.x);
+      dst[ia] = A.plain ? (T)z.x : (T)((CT)dst[ia] + z.x);
       if (2 * p + 1 < Q) {
         const int64_t ib = (2 * p + 1) * NS + s;
-        dst[ib] = (T)((CT)dst[ib] + z.y);
+        dst[ib] = A.plain ? (T)z.y : (T)((CT)dst[ib] + z.y);
       }
     }
   }

@@ -60,6 +60,7 @@ class SolverBase {
   virtual msc_status bdf2_adjoint(int32_t nsteps, double* lam, bool on_device) = 0;
   virtual msc_status init_adjoint(const double* phat0, const double* u0, const double* lam, double* lam_phat0,
                                   double* lam_u0, bool on_device) = 0;
+  virtual void krylov_stats(int64_t* solves, int64_t* iters, int64_t* refreshes, double* worst) const = 0;
   virtual Tuning& tuning() = 0;
   virtual msc_status reconfigure() = 0;  // re-pick launch shapes after a tuning change
 

@@ -14,6 +14,7 @@
 
 #include "msc_adjoint.h"
 #include "msc_fullsym.h"
+#include "msc_walls.h"
 #include "msc_solver.h"
 
 namespace msc {
@@ -142,6 +143,13 @@ class Solver : public SolverBase {
 
   Tuning& tuning() override { return tune; }
 
+  void krylov_stats(int64_t* solves, int64_t* iters, int64_t* refreshes, double* worst) const override {
+    if (solves) *solves = kr_solves;
+    if (iters) *iters = kr_iters;
+    if (refreshes) *refreshes = kr_refresh;
+    if (worst) *worst = kr_worst;
+  }
+
   msc_status reconfigure() override {
     return guard([&]() {
       sync();
@@ -162,12 +170,21 @@ class Solver : public SolverBase {
         last_error = "the shadow corrector is not available for this lattice/grid size";
         return MSC_ERR_UNSUPPORTED;
       }
+      if (wallkin() && !wall_supported()) {
+        last_error = "the wall-kinetic corrector needs the D2Q9 cavity, FP64 storage, tau+ = tau- = 1 and "
+                     "extents up to 256";
+        return MSC_ERR_UNSUPPORTED;
+      }
       if (fullsym() && !fs_supported()) {
         last_error = "the full-symbol corrector needs D2Q9 with FP64 or FP32 storage and its transforms "
                      "in LDS (N_x, N_y <= 512 FP32 / 256 FP64 per line pass)";
         return MSC_ERR_UNSUPPORTED;
       }
       allocate();
+      // Algorithm 2: the initial wall operator is assembled at rest with the
+      // BDF2 coefficient
+      wk_aA = 1.5 / P.dt;
+      wk_rest = true;
       const int64_t NS = G.NS;
       double* pd = nullptr;
       double* ud = nullptr;
@@ -205,6 +222,7 @@ class Solver : public SolverBase {
 
   // ------------------------------------------------------- BDF dual time --
   msc_status bdf2_step(int32_t nsteps, msc_step_stats* out) override {
+    if (wallkin()) return bdf2_step_walls(nsteps, out);
     return guard([&]() -> msc_status {
       if (nsteps <= 0) return MSC_OK;
       ensure_stats(nsteps);
@@ -410,6 +428,7 @@ class Solver : public SolverBase {
   msc_status correct(const double* f, const double* h_in, double a, double* fnext, double* dm_out,
                      double* R) override {
     if (fullsym()) return correct_fullsym(f, h_in, a, fnext, dm_out, R);
+    if (wallkin()) return correct_walls(f, h_in, a, fnext, dm_out, R);
     return guard([&]() -> msc_status {
       if (!corrector_supported()) {
         last_error = "the shadow corrector is not available for this lattice/grid";
@@ -465,6 +484,292 @@ class Solver : public SolverBase {
       sync();
       if (dm_out) std::memset(dm_out, 0, sizeof(double) * (D + 1) * G.NS);
       return MSC_OK;
+    });
+  }
+
+  // ------------------------------------------- wall-bounded correction --
+  void wall_allocate() {
+    const int64_t n = (int64_t)Q * G.NS;
+    wk_m = P.wall_restart > 0 ? P.wall_restart : 50;
+    wk_V = keep((double*)dalloc(sizeof(double) * (wk_m + 1) * n));
+    wk_R = keep((double*)dalloc(sizeof(double) * n));
+    wk_Y = keep((double*)dalloc(sizeof(double) * n));
+    wk_Z = keep((double*)dalloc(sizeof(double) * n));
+    wk_D = keep((double*)dalloc(sizeof(double) * n));
+    wk_mu = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
+    wk_mref = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
+    wk_sref = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
+    wk_part = keep((double*)dalloc(sizeof(double) * kDotBlocks * (wk_m + 1)));
+    wk_coef = keep((double*)dalloc(sizeof(double) * (wk_m + 1)));
+    MSC_HIPCK(hipHostMalloc((void**)&wk_part_h, sizeof(double) * kDotBlocks * (wk_m + 1), hipHostMallocDefault));
+    MSC_HIPCK(hipHostMalloc((void**)&wk_coef_h, sizeof(double) * (wk_m + 1), hipHostMallocDefault));
+  }
+
+  int vec_grid() const {
+    const int64_t n = (int64_t)Q * G.NS;
+    return (int)std::min<int64_t>((n + 255) / 256, 2048);
+  }
+
+  // <V_i, w> for i < nv, summed on the host in block order
+  void wall_dots(const double* V, int nv, const double* w, double* out) {
+    const int64_t n = (int64_t)Q * G.NS;
+    hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, V, n, nv, w, n, wk_part);
+    MSC_HIPCK(hipGetLastError());
+    MSC_HIPCK(hipMemcpyAsync(wk_part_h, wk_part, sizeof(double) * kDotBlocks * nv, hipMemcpyDeviceToHost, st));
+    sync();
+    for (int i = 0; i < nv; ++i) {
+      double acc = 0.0;
+      for (int b = 0; b < kDotBlocks; ++b) acc += wk_part_h[(int64_t)i * kDotBlocks + b];
+      out[i] = acc;
+    }
+  }
+
+  void upload_coef(const double* c, int nv) {
+    for (int i = 0; i < nv; ++i) wk_coef_h[i] = c[i];
+    MSC_HIPCK(hipMemcpyAsync(wk_coef, wk_coef_h, sizeof(double) * nv, hipMemcpyHostToDevice, st));
+  }
+
+  void lincomb(double* out, const double* x, double alpha, const double* y, double beta) {
+    hipLaunchKernelGGL(k_lincomb<0>, dim3(vec_grid()), dim3(256), 0, st, out, x, alpha, y, beta,
+                       (int64_t)Q * G.NS);
+    MSC_HIPCK(hipGetLastError());
+  }
+
+  // w = (I - L) z with the current operator (Eq. wall-global-jacobian)
+  void wall_apply(const double* z, double* w) {
+    const int g = ew_grid();
+    hipLaunchKernelGGL(k_wall_mu<0>, dim3(g), dim3(256), 0, st, z, wk_mu, G.NS, 1.0 / (1.0 + 0.5 * wk_aA));
+    MSC_HIPCK(hipGetLastError());
+    hipLaunchKernelGGL(k_wall_apply<0>, dim3(g), dim3(256), 0, st, z, (const double*)wk_mu,
+                       wk_rest ? (const double*)nullptr : (const double*)wk_mref,
+                       wk_rest ? (const double*)nullptr : (const double*)wk_sref, wk_aA, G.N0, G.N2, w);
+    MSC_HIPCK(hipGetLastError());
+  }
+
+  // out = M^{-1} in: the periodic full-symbol inverse at rest (omega = 1, a_A)
+  void wall_precondition(const double* in, double* out) {
+    if constexpr (std::is_same<T, double>::value && std::is_same<TM, double>::value)
+      enqueue_fullsym(nullptr, 0, 0, wk_aA, nullptr, nullptr, true, true, (T*)out, (const TM*)in, 1);
+  }
+
+  // Restarted GMRES(m), right-preconditioned, classical Gram-Schmidt with one
+  // re-orthogonalisation: delta ~ (I - L)^{-1} rhs to the relative residual
+  // krylov_tol.  Returns the iteration count; rel receives the final true
+  // relative residual.
+  int wall_gmres(const double* rhs, double* delta, double& rel) {
+    const int64_t n = (int64_t)Q * G.NS;
+    const int m = wk_m;
+    const double tol = P.krylov_tol > 0.0 ? P.krylov_tol : 1e-12;
+    const int max_restarts = 40;
+    double b2 = 0.0;
+    wall_dots(rhs, 1, rhs, &b2);
+    const double beta0 = std::sqrt(b2);
+    lincomb(delta, rhs, 0.0, nullptr, 0.0);
+    rel = 0.0;
+    if (!(beta0 > 0.0)) return 0;
+    if (!std::isfinite(beta0)) {
+      rel = beta0;
+      return 0;
+    }
+    lincomb(wk_R, rhs, 1.0, nullptr, 0.0);
+    double beta = beta0;
+    int iters = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
+    for (int rs = 0; rs < max_restarts; ++rs) {
+      lincomb(wk_V, wk_R, 1.0 / beta, nullptr, 0.0);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jend = 0;
+      bool done = false;
+      for (int j = 0; j < m; ++j) {
+        double* vj1 = wk_V + (int64_t)(j + 1) * n;
+        wall_precondition(wk_V + (int64_t)j * n, wk_Z);
+        wall_apply(wk_Z, vj1);
+        wall_dots(wk_V, j + 1, vj1, h.data());
+        upload_coef(h.data(), j + 1);
+        hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
+                           (const double*)wk_coef, n);
+        MSC_HIPCK(hipGetLastError());
+        wall_dots(wk_V, j + 1, vj1, h2.data());
+        upload_coef(h2.data(), j + 1);
+        hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
+                           (const double*)wk_coef, n);
+        MSC_HIPCK(hipGetLastError());
+        for (int i = 0; i <= j; ++i) h[i] += h2[i];
+        double hn2 = 0.0;
+        wall_dots(vj1, 1, vj1, &hn2);
+        const double hn = std::sqrt(hn2);
+        if (hn > 0.0) lincomb(vj1, vj1, 1.0 / hn, nullptr, 0.0);
+        // Givens rotations on the new column
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+          h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+          h[i] = t;
+        }
+        const double den = std::hypot(h[j], hn);
+        cs[j] = den > 0.0 ? h[j] / den : 1.0;
+        sn[j] = den > 0.0 ? hn / den : 0.0;
+        h[j] = den;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+        ++iters;
+        jend = j + 1;
+        if (std::fabs(g[j + 1]) <= tol * beta0 || !(hn > 0.0)) {
+          done = true;
+          break;
+        }
+      }
+      // y = H^{-1} g (upper triangular), delta += M^{-1} V y
+      for (int i = jend - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
+        y[i] = acc / H[(size_t)i * m + i];
+      }
+      upload_coef(y.data(), jend);
+      hipLaunchKernelGGL(k_combine<0>, dim3(vec_grid()), dim3(256), 0, st, wk_Y, (const double*)wk_V, n, jend,
+                         (const double*)wk_coef, n);
+      MSC_HIPCK(hipGetLastError());
+      wall_precondition(wk_Y, wk_Z);
+      lincomb(delta, delta, 1.0, wk_Z, 1.0);
+      // true residual
+      wall_apply(delta, wk_Y);
+      lincomb(wk_R, rhs, 1.0, wk_Y, -1.0);
+      double r2 = 0.0;
+      wall_dots(wk_R, 1, wk_R, &r2);
+      beta = std::sqrt(r2);
+      rel = beta / beta0;
+      if (done || rel <= tol || !(beta > 0.0)) break;
+    }
+    kr_solves += 1;
+    kr_iters += iters;
+    kr_worst = std::max(kr_worst, rel);
+    return iters;
+  }
+
+  // f_T <- f_T + (delta - r) = f + delta, f the sweep's input
+  void wall_update(double* fT, const double* delta, const double* r) {
+    lincomb(wk_Y, delta, 1.0, r, -1.0);
+    lincomb(fT, fT, 1.0, wk_Y, 1.0);
+  }
+
+  // Algorithm 2 driven from the host: each inner iteration is the sweep (with
+  // the wall rows) and the device-side acceptance decision, then, when the
+  // step goes on, the residual guard (adaptive branch) and the correction.
+  msc_status bdf2_step_walls(int32_t nsteps, msc_step_stats* out) {
+    return guard([&]() -> msc_status {
+      if constexpr (std::is_same<T, double>::value) {
+        if (nsteps <= 0) return MSC_OK;
+        ensure_stats(nsteps);
+        const int stat_base = n_next;
+        const bool use_sched = sched_pos < (int64_t)sched_h.size();
+        if (use_sched) {
+          std::vector<int32_t> K(nsteps, 0);
+          for (int i = 0; i < nsteps; ++i) {
+            const int64_t j = sched_pos + i;
+            K[i] = (j < (int64_t)sched_h.size()) ? sched_h[j] : P.k_max;
+          }
+          ensure_sched(nsteps);
+          MSC_HIPCK(hipMemcpyAsync(sched_d, K.data(), sizeof(int32_t) * nsteps, hipMemcpyHostToDevice, st));
+        }
+        wall_refreshes.assign(nsteps, 0);
+        const int64_t NS = G.NS;
+        double Rdev = 0.0;
+        for (int i = 0; i < nsteps; ++i) {
+          const int n = n_next;
+          const int64_t bc = bdf_count;
+          const int q = (bc == 0) ? 1 : 2;
+          const int max_order = (P.extrap_states == 0) ? 2 : P.extrap_states - 1;
+          const int order = (int)std::min<int64_t>(bc, max_order);
+          const double a = (q == 1) ? 1.0 / P.dt : 3.0 / (2.0 * P.dt);
+          int n_grow = 0, n_ref = 0;
+          double Rref = 0.0, Rprev = 0.0;
+          for (int ell = 1; ell <= P.k_max; ++ell) {
+            enqueue_iteration(n, ell, q, order, a, use_sched, stat_base, true);
+            MSC_HIPCK(hipMemcpyAsync(ctl_h, ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
+            MSC_HIPCK(hipMemcpyAsync(&Rdev, Rhist + (ell - 1), sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            const uint32_t ps = phase_state(ctl_h->phase);
+            if (ps == PH_ACCEPTED) {
+              bdf_count += 1;
+              n_next = n + 1;
+              last_iters = ell;
+              break;
+            }
+            if (ps == PH_FAILED) {
+              const msc_status rc = (ctl_h->fail_code == 5) ? MSC_ERR_NONCONVERGED : MSC_ERR_NONFINITE;
+              last_error = std::string(rc == MSC_ERR_NONCONVERGED ? "nonconvergent" : "non-finite residual") +
+                           " at physical step " + std::to_string(n) + ", inner iteration " + std::to_string(ell);
+              ctl_h->phase = make_phase(n - 1, 0, PH_ACCEPTED);
+              ctl_h->fail_code = 0;
+              MSC_HIPCK(hipMemcpyAsync(ctl, ctl_h, sizeof(DevCtl), hipMemcpyHostToDevice, st));
+              copy_stats(out, stat_base, n - stat_base + 1);
+              if (use_sched) sched_pos += (n - stat_base);
+              sync();
+              return rc;
+            }
+            // Algorithm 2: residual guard of the adaptive operator
+            const double R = Rdev;
+            if (ell == 1) Rref = R;
+            n_grow = (ell > 1 && R > Rprev) ? n_grow + 1 : 0;
+            Rprev = R;
+            T* fT = fb.p[ctl_h->roles[n & 1].slot_w[ell & 1]];
+            if (P.wall_operator == MSC_WALL_ADAPTIVE && n_ref < 3 &&
+                (n_grow >= 2 || R > 10.0 * Rref || (P.wall_forced > 0 && ell % P.wall_forced == 0))) {
+              hipLaunchKernelGGL(k_wall_reference<0>, dim3(ew_grid()), dim3(256), 0, st, (const double*)fT,
+                                 (const double*)rfs, (const double*)h, a, NS, wk_mref, wk_sref);
+              MSC_HIPCK(hipGetLastError());
+              wk_aA = a;
+              wk_rest = false;
+              ++n_ref;
+              ++kr_refresh;
+              wall_refreshes[i] = n_ref;
+              n_grow = 0;
+              Rref = R;
+            }
+            double rel = 0.0;
+            wall_gmres(rfs, wk_D, rel);
+            wall_update(fT, wk_D, rfs);
+          }
+        }
+        copy_stats(out, stat_base, nsteps);
+        if (use_sched) sched_pos += nsteps;
+        return MSC_OK;
+      } else {
+        (void)nsteps, (void)out;
+        return MSC_ERR_UNSUPPORTED;
+      }
+    });
+  }
+
+  // One wall-corrected iteration from host arrays with the current operator.
+  msc_status correct_walls(const double* f, const double* h_in, double a, double* fnext, double* dm_out,
+                           double* R) {
+    return guard([&]() -> msc_status {
+      if constexpr (std::is_same<T, double>::value) {
+        pull_ctl();
+        T* A = fb.p[cur_roles().slot_w[0]];
+        T* B = fb.p[cur_roles().slot_w[1]];
+        upload_pop(f, A);
+        upload_h(h_in);
+        SweepArgs<T, TM> S = sweep_args(a);
+        S.src = A;
+        S.dst = B;
+        S.rout = rfs;
+        launch_sweep_timed(SW_DTS, S, 0);
+        const double Rv = reduce_partials(S);
+        if (R) *R = Rv;
+        double rel = 0.0;
+        wall_gmres(rfs, wk_D, rel);
+        wall_update(B, wk_D, rfs);
+        if (fnext) download_pop(B, fnext);
+        sync();
+        if (dm_out) std::memset(dm_out, 0, sizeof(double) * (D + 1) * G.NS);
+        return MSC_OK;
+      } else {
+        (void)f, (void)h_in, (void)a, (void)fnext, (void)dm_out, (void)R;
+        return MSC_ERR_UNSUPPORTED;
+      }
     });
   }
 
@@ -543,8 +848,8 @@ class Solver : public SolverBase {
         last_error = "the FP64 transforms of the adjoint correction do not fit this grid size";
         return MSC_ERR_UNSUPPORTED;
       }
-      if (fullsym()) {
-        last_error = "the adjoint covers the Picard and shadow correctors only";
+      if (fullsym() || wallkin() || walls()) {
+        last_error = "the adjoint covers the periodic Picard and shadow marches only";
         return MSC_ERR_UNSUPPORTED;
       }
       int kmax = 1;
@@ -639,7 +944,29 @@ class Solver : public SolverBase {
   cpx<CT>* spec = nullptr;
   cpx<CT>* spec2 = nullptr;
   cpx<CT>* spec_alt = nullptr;  // 2D: second band spectrum (inverse rows in the sweep)
-  TM* rfs = nullptr;           // full symbol: residual of every field (Q x NS)
+  TM* rfs = nullptr;           // full symbol / wall corrector: residual of every field (Q x NS)
+  // wall-bounded kinetic corrector (Algorithm 2): Krylov basis and work
+  // vectors (FP64, Q x NS each), the reference field of the current operator
+  // and the assembly coefficient a_A, dot-product partials and coefficients
+  double* wk_V = nullptr;
+  double* wk_R = nullptr;
+  double* wk_Y = nullptr;
+  double* wk_Z = nullptr;
+  double* wk_D = nullptr;
+  double* wk_mu = nullptr;
+  double* wk_mref = nullptr;
+  double* wk_sref = nullptr;
+  double* wk_part = nullptr;
+  double* wk_part_h = nullptr;
+  double* wk_coef = nullptr;
+  double* wk_coef_h = nullptr;
+  int wk_m = 50;
+  double wk_aA = 0.0;
+  bool wk_rest = true;
+  static constexpr int kDotBlocks = 256;
+  int64_t kr_solves = 0, kr_iters = 0, kr_refresh = 0;
+  double kr_worst = 0.0;
+  std::vector<int32_t> wall_refreshes;
   cpx<CT>* spec_fs = nullptr;  // full symbol: half spectrum (Q x N_x x (N_y/2 + 1))
   double* partials = nullptr;
   double* partials_h = nullptr;
@@ -767,6 +1094,12 @@ class Solver : public SolverBase {
   bool corrector_supported() const { return fft_fits(); }
 
   bool fullsym() const { return P.corrector == MSC_CORRECTOR_FULL_SYMBOL; }
+  bool wallkin() const { return P.corrector == MSC_CORRECTOR_WALL_KINETIC; }
+  bool walls() const { return P.boundary == MSC_BOUNDARY_CAVITY; }
+  bool wall_supported() const {
+    return D == 2 && std::is_same<T, double>::value && walls() && P.tau_plus == 1.0 && P.tau_minus == 1.0 &&
+           fs_supported();
+  }
   // the full-symbol passes at their minimum block shape: one row of
   // (Q+1)/2 packed lines, one column of Q lines, each with its LDS ping-pong
   bool fs_supported(size_t c = sizeof(cpx<CT>)) const {
@@ -812,7 +1145,8 @@ class Solver : public SolverBase {
       }
       set_fft_attrs();
     }
-    if (fullsym() && fs_supported()) {
+    if (wallkin() && wall_supported()) wall_allocate();
+    if ((fullsym() || wallkin()) && fs_supported()) {
       rfs = keep((TM*)dalloc(sizeof(TM) * (int64_t)Q * NS));
       spec_fs = keep((cpx<CT>*)dalloc(sizeof(cpx<CT>) * (int64_t)Q * G.N0 * (G.N2 / 2 + 1)));
       if (!tw[0]) tw[0] = make_twiddles(G.N0);
@@ -845,6 +1179,10 @@ class Solver : public SolverBase {
     if (partials_h) (void)hipHostFree(partials_h);
     if (run_flags_h) (void)hipHostFree(run_flags_h);
     run_flags_h = nullptr;
+    if (wk_part_h) (void)hipHostFree(wk_part_h);
+    if (wk_coef_h) (void)hipHostFree(wk_coef_h);
+    wk_part_h = nullptr;
+    wk_coef_h = nullptr;
     ctl_h = nullptr;
     stats_h = nullptr;
     partials_h = nullptr;
@@ -904,7 +1242,7 @@ class Solver : public SolverBase {
       out[i].R_final = stats_h[i].R_final;
       out[i].rho_obs = stats_h[i].rho_obs;
       out[i].converged = stats_h[i].converged;
-      out[i].reserved = 0;
+      out[i].refreshes = (i < (int)wall_refreshes.size()) ? wall_refreshes[i] : 0;
     }
   }
 
@@ -1334,6 +1672,8 @@ class Solver : public SolverBase {
     S.wm = wm;
     S.sig = sig;
     S.isig = 1.0f / sig;
+    S.walls = walls() ? 1 : 0;
+    S.ulid = P.u_lid;
     return S;
   }
 
@@ -1484,7 +1824,7 @@ class Solver : public SolverBase {
       mode = fuse_inv ? SW_DTS_LIFT_ROWS : SW_DTS_LIFT;
     else
       mode = SW_DTS;
-    if (fullsym()) S.rout = rfs;
+    if (fullsym() || wallkin()) S.rout = rfs;
     if (fuse_rows) {
       S.fuse_rows = 1;
       S.lgr = ilog2(G.N2);
@@ -1651,7 +1991,8 @@ class Solver : public SolverBase {
   // inverse rows pass, which leave f_{l+1} in the sweep's output buffer (out
   // when c is null).
   void enqueue_fullsym(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac,
-                       const FinishArgs* Fin, bool head, bool tail, T* out) {
+                       const FinishArgs* Fin, bool head, bool tail, T* out, const TM* rin = nullptr,
+                       int plain = 0) {
     if constexpr (D == 2 && !DV) {
       FsArgs<T, CT, TM> F{};
       F.g = CorrGuard{c, n, ell};
@@ -1663,7 +2004,8 @@ class Solver : public SolverBase {
       F.NH = G.N2 / 2 + 1;
       F.rows_per_block = fs_rows_per_block();
       F.cols_per_block = fs_cols_per_block();
-      F.r = rfs;
+      F.r = rin ? rin : rfs;
+      F.plain = plain;
       F.spec = spec_fs;
       F.twx = tw[0];
       F.twy = tw[2];
@@ -1689,7 +2031,8 @@ class Solver : public SolverBase {
         MSC_HIPCK(hipGetLastError());
       }
     } else {
-      (void)c, (void)n, (void)ell, (void)a, (void)Ac, (void)Fin, (void)head, (void)tail, (void)out;
+      (void)c, (void)n, (void)ell, (void)a, (void)Ac, (void)Fin, (void)head, (void)tail, (void)out, (void)rin,
+          (void)plain;
     }
   }
 

@@ -207,6 +207,9 @@ struct SweepArgs {
   // SW_DTS_LIFT_ROWS: the solved band spectrum of the previous correction
   // ([field][x][j <= N_y/4]), inverted along y by the sweep to give dm
   const cpx<TM>* spec_in;
+  // D2Q9 lid-driven cavity: wall rows after streaming (every mode)
+  int walls;
+  double ulid;
 };
 
 // ---- compile-time direction classification -----------------------------
@@ -700,6 +703,9 @@ __global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
             const int g = xgroup<L>(k), gi = group_index<L>(k);
             vv[k] = (g == 0) ? (CT)ldsP[rP][gi][s] : ((g == 1) ? (CT)ldsZ[rZ][gi][s] : (CT)ldsM[rM][gi][s]);
           }
+        }
+        if constexpr (L::D == 2) {
+          if (A.walls) cavity_rows<CT>(vv, xd, b2 + i2, N0, N2, (CT)A.ulid);
         }
         if constexpr (PopDev<T>::value) {
           // store (g, M); the residual is then taken against the stored

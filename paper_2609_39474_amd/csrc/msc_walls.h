@@ -1,0 +1,186 @@
+// Wall-bounded kinetic correction (paper Sec. 3.3, Algorithm 2) on the D2Q9
+// lid-driven cavity: (I - L) df = r with L = B_Gamma S blkdiag(J^C(x))
+// (Eq. wall-global-jacobian).  J^C(x) is the local collision Jacobian of Eq.
+// (wall-local-jacobian) at a reference field (m, s): with G of Eq. (wall-G),
+// J^C_kk' = (G_k0 + sum_a G_ka c_k'a) / (1 + a/2), i.e. (J^C z)_k =
+// sum_b G_kb mu_b with mu = P z / (1 + a/2).  S streams with the periodic
+// wrap, B_Gamma replaces the wall rows in the order of Eq. (bounceback-rows)
+// (the lid constants have zero derivative).
+//
+// The paper factors I - L with a sparse direct solver.  Here it is solved by
+// restarted GMRES, preconditioned on the right with the periodic full-symbol
+// inverse at rest (the transform kernels of msc_fullsym.h in plain mode):
+// away from the walls the two operators coincide, so the preconditioned
+// operator is the identity plus a perturbation supported on the wall rows.
+// The kernels below are the matrix-free operator and the Krylov vector
+// operations (FP64, fixed-order block partial sums, so results do not depend
+// on scheduling).
+#pragma once
+
+#include "msc_fullsym.h"
+
+namespace msc {
+
+// Eq. (wall-G) at omega+- = 1 for direction k (D2Q9): G[0] = dC_k/dp,
+// G[1 + b] = dC_k/du_b at the reference moments m and source s.
+__device__ inline void wall_G(int k, const double* m, const double* s, double a, double* G) {
+  const double cs2 = 1.0 / 3.0, cs4 = cs2 * cs2;
+  const double wk = D2Q9::w(k);
+  const double c0 = (double)D2Q9::cx(k), c1 = (double)D2Q9::cy(k);
+  const double cu = c0 * m[1] + c1 * m[2];
+  G[0] = wk * (1.0 - 0.5 * a);
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const double cb = (b == 0) ? c0 : c1, ub = m[1 + b];
+    double g = wk * (cb / cs2 + cu * cb / cs4 - ub / cs2);
+    double src = 0.0;
+#pragma unroll
+    for (int al = 0; al < 2; ++al) {
+      const double ca_ = (al == 0) ? c0 : c1;
+      src += (-(al == b ? 1.0 : 0.0) / cs2 + ca_ * cb / cs4) * s[1 + al];
+    }
+    src -= a * ((cb - ub) / cs2 + cu * cb / cs4);
+    G[1 + b] = g + 0.5 * wk * src;
+  }
+}
+
+// mu = P z / (1 + a/2) at every site (3 fields).
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_wall_mu(const double* __restrict__ z, double* __restrict__ mu, int64_t NS,
+                                                 double inv1pa2) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += (int64_t)gridDim.x * blockDim.x) {
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double v = z[k * NS + s];
+      m0 += v;
+      m1 += (double)D2Q9::cx(k) * v;
+      m2 += (double)D2Q9::cy(k) * v;
+    }
+    mu[s] = m0 * inv1pa2;
+    mu[NS + s] = m1 * inv1pa2;
+    mu[2 * NS + s] = m2 * inv1pa2;
+  }
+}
+
+// w = z - L z at every destination node: the streamed rows (J^C(x) z(x))_k
+// from the upwind site x = y - c_k (periodic wrap), then the wall rows of the
+// node replaced in order.  mref/sref: the reference field ((d+1) x N_sites
+// each), or null for the uniform rest reference (m = (1, 0), s = 0).
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_wall_apply(const double* __restrict__ z, const double* __restrict__ mu,
+                                                    const double* __restrict__ mref,
+                                                    const double* __restrict__ sref, double a, int Nx, int Ny,
+                                                    double* __restrict__ w) {
+  const int64_t NS = (int64_t)Nx * Ny;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(s / Ny), y = (int)(s - (int64_t)x * Ny);
+    double Lz[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      int xu = x - D2Q9::cx(k), yu = y - D2Q9::cy(k);
+      xu = (xu < 0) ? xu + Nx : (xu >= Nx ? xu - Nx : xu);
+      yu = (yu < 0) ? yu + Ny : (yu >= Ny ? yu - Ny : yu);
+      const int64_t su = (int64_t)xu * Ny + yu;
+      double m[3] = {1.0, 0.0, 0.0}, sv[3] = {0.0, 0.0, 0.0}, G[3];
+      if (mref) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          m[b] = mref[b * NS + su];
+          sv[b] = sref[b * NS + su];
+        }
+      }
+      wall_G(k, m, sv, a, G);
+      Lz[k] = G[0] * mu[su] + G[1] * mu[NS + su] + G[2] * mu[2 * NS + su];
+    }
+    cavity_rows<double>(Lz, x, y, Nx, Ny, 0.0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k * NS + s] = z[k * NS + s] - Lz[k];
+  }
+}
+
+// Reference field of a refresh (Algorithm 2): the current iterate f = f_T - r
+// reconstructed with the unchanged history term, m = (P f + h/2)/(1 + a/2),
+// s = h - a m.
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_wall_reference(const double* __restrict__ fT, const double* __restrict__ r,
+                                                        const double* __restrict__ h, double a, int64_t NS,
+                                                        double* __restrict__ mref, double* __restrict__ sref) {
+  const double inv = 1.0 / (1.0 + 0.5 * a);
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += (int64_t)gridDim.x * blockDim.x) {
+    double M[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double f = fT[k * NS + s] - r[k * NS + s];
+      M[0] += f;
+      M[1] += (double)D2Q9::cx(k) * f;
+      M[2] += (double)D2Q9::cy(k) * f;
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double m = (M[b] + 0.5 * h[b * NS + s]) * inv;
+      mref[b * NS + s] = m;
+      sref[b * NS + s] = h[b * NS + s] - a * m;
+    }
+  }
+}
+
+// ------------------------------------------------------- Krylov helpers --
+// partials[i * gridDim.x + block] = this block's part of <V_i, w>, i < nv
+// (V_i = V + i * stride); the caller sums the partials in block order.
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int64_t stride, int nv,
+                                              const double* __restrict__ w, int64_t n,
+                                              double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * chunk;
+  const int64_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
+  for (int i = 0; i < nv; ++i) {
+    const double* v = V + i * stride;
+    double acc = 0.0;
+    for (int64_t t = b0 + threadIdx.x; t < b1; t += blockDim.x) acc += v[t] * w[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) sum += red[wv];
+      partials[(int64_t)i * gridDim.x + blockIdx.x] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// w -= sum_i coef[i] V_i (coef on the device), i < nv.
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_axpy_multi(double* __restrict__ w, const double* __restrict__ V, int64_t stride,
+                                                    int nv, const double* __restrict__ coef, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = w[t];
+    for (int i = 0; i < nv; ++i) acc -= coef[i] * V[i * stride + t];
+    w[t] = acc;
+  }
+}
+
+// out = sum_i coef[i] V_i, i < nv.
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, const double* __restrict__ V, int64_t stride,
+                                                 int nv, const double* __restrict__ coef, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < nv; ++i) acc += coef[i] * V[i * stride + t];
+    out[t] = acc;
+  }
+}
+
+// out = alpha * x + beta * y (any of x, y may alias out).
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_lincomb(double* out, const double* x, double alpha, const double* y,
+                                                 double beta, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = alpha * x[t] + (y ? beta * y[t] : 0.0);
+}
+
+}  // namespace msc

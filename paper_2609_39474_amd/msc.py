@@ -34,6 +34,11 @@ MSC_D3Q19 = 3
 MSC_CORRECTOR_PICARD = 0
 MSC_CORRECTOR_SHADOW = 1
 MSC_CORRECTOR_FULL_SYMBOL = 2
+MSC_CORRECTOR_WALL_KINETIC = 3
+MSC_BOUNDARY_PERIODIC = 0
+MSC_BOUNDARY_CAVITY = 1
+MSC_WALL_FROZEN = 0
+MSC_WALL_ADAPTIVE = 1
 MSC_STORAGE_FP64 = 0
 MSC_STORAGE_FP32 = 1
 MSC_STORAGE_FP16_DEV = 2
@@ -60,6 +65,12 @@ class msc_params(ctypes.Structure):
         ("alloc_fn", ALLOC_FN),
         ("free_fn", FREE_FN),
         ("alloc_user", ctypes.c_void_p),
+        ("boundary", ctypes.c_int32),
+        ("wall_operator", ctypes.c_int32),
+        ("u_lid", ctypes.c_double),
+        ("wall_forced", ctypes.c_int32),
+        ("wall_restart", ctypes.c_int32),
+        ("krylov_tol", ctypes.c_double),
     ]
 
 
@@ -71,7 +82,7 @@ class msc_step_stats(ctypes.Structure):
         ("R_final", ctypes.c_double),
         ("rho_obs", ctypes.c_double),
         ("converged", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("refreshes", ctypes.c_int32),
     ]
 
 
@@ -100,6 +111,8 @@ SIGNATURES = {
     "msc_set_state": (ctypes.c_int, [_vp, _dp, ctypes.c_int64]),
     "msc_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "msc_kernel_time": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int64), _dp]),
+    "msc_krylov_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64), _dp]),
     "msc_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "msc_set_recording": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "msc_recorded_steps": (ctypes.c_int, [_vp, _ip]),
@@ -239,7 +252,7 @@ class Solver:
         st = (msc_step_stats * max(1, nsteps))()
         rc = lib().msc_bdf2_step(self.h, nsteps, st)
         stats = [dict(q=s.q, iters=s.iters, R_first=s.R_first, R_final=s.R_final, rho_obs=s.rho_obs,
-                      converged=s.converged) for s in st[:nsteps]]
+                      converged=s.converged, refreshes=s.refreshes) for s in st[:nsteps]]
         if rc != MSC_OK and raise_on_fail:
             self._check(rc, "msc_bdf2_step")
         return rc, stats
@@ -331,6 +344,15 @@ class Solver:
                     "msc_kernel_time")
         return sec.value, n.value, b.value
 
+    def krylov_stats(self):
+        """(solves, GMRES iterations, refreshes, worst final relative residual)
+        of the wall corrector since creation."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        w = ctypes.c_double()
+        self._check(lib().msc_krylov_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                           ctypes.byref(w)), "msc_krylov_stats")
+        return a.value, b.value, c.value, w.value
+
     def set_tuning(self, key, value):
         self._check(lib().msc_set_tuning(self.h, key, value), "msc_set_tuning")
 
@@ -368,11 +390,18 @@ class Solver:
 
 
 def make_params(d, N, *, dt, eps, storage="fp64", corrector="shadow", tau_plus=1.0, tau_minus=1.0,
-                k_max=300, n_min=None, extrap_states=0):
+                k_max=300, n_min=None, extrap_states=0, boundary="periodic", u_lid=0.0, wall_operator="frozen",
+                wall_forced=0, wall_restart=0, krylov_tol=0.0):
     p = msc_params_default(MSC_D2Q9 if d == 2 else MSC_D3Q19, N, dt, eps)
     p.storage = {"fp64": MSC_STORAGE_FP64, "fp32": MSC_STORAGE_FP32, "fp16dev": MSC_STORAGE_FP16_DEV}[storage]
     p.corrector = {"shadow": MSC_CORRECTOR_SHADOW, "picard": MSC_CORRECTOR_PICARD,
-                   "full_symbol": MSC_CORRECTOR_FULL_SYMBOL}[corrector]
+                   "full_symbol": MSC_CORRECTOR_FULL_SYMBOL, "wall_kinetic": MSC_CORRECTOR_WALL_KINETIC}[corrector]
+    p.boundary = {"periodic": MSC_BOUNDARY_PERIODIC, "cavity": MSC_BOUNDARY_CAVITY}[boundary]
+    p.u_lid = u_lid
+    p.wall_operator = {"frozen": MSC_WALL_FROZEN, "adaptive": MSC_WALL_ADAPTIVE}[wall_operator]
+    p.wall_forced = wall_forced
+    p.wall_restart = wall_restart
+    p.krylov_tol = krylov_tol
     p.tau_plus = tau_plus
     p.tau_minus = tau_minus
     p.k_max = k_max
