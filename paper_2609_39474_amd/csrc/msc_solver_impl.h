@@ -574,7 +574,7 @@ class Solver : public SolverBase {
     lincomb(wk_R, rhs, 1.0, nullptr, 0.0);
     double beta = beta0;
     int iters = 0;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 2), h2(m + 2), y(m);
     for (int rs = 0; rs < max_restarts; ++rs) {
       lincomb(wk_V, wk_R, 1.0 / beta, nullptr, 0.0);
       std::fill(g.begin(), g.end(), 0.0);
@@ -590,16 +590,20 @@ class Solver : public SolverBase {
         hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
                            (const double*)wk_coef, n);
         MSC_HIPCK(hipGetLastError());
-        wall_dots(wk_V, j + 1, vj1, h2.data());
+        // re-orthogonalisation: <V_i, w> for i <= j and <w, w> in one pass
+        // (V_{j+1} is w itself), then w <- (w - V h2)/|w - V h2| with
+        // |w - V h2|^2 = <w, w> - |h2|^2 (w - V h2 is orthogonal to V)
+        wall_dots(wk_V, j + 2, vj1, h2.data());
+        double ww = h2[j + 1], hh = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          h[i] += h2[i];
+          hh += h2[i] * h2[i];
+        }
+        const double hn = std::sqrt(std::max(ww - hh, 0.0));
         upload_coef(h2.data(), j + 1);
-        hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
-                           (const double*)wk_coef, n);
+        hipLaunchKernelGGL(k_axpy_scale<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
+                           (const double*)wk_coef, hn > 0.0 ? 1.0 / hn : 1.0, n);
         MSC_HIPCK(hipGetLastError());
-        for (int i = 0; i <= j; ++i) h[i] += h2[i];
-        double hn2 = 0.0;
-        wall_dots(vj1, 1, vj1, &hn2);
-        const double hn = std::sqrt(hn2);
-        if (hn > 0.0) lincomb(vj1, vj1, 1.0 / hn, nullptr, 0.0);
         // Givens rotations on the new column
         for (int i = 0; i < j; ++i) {
           const double t = cs[i] * h[i] + sn[i] * h[i + 1];

@@ -164,6 +164,17 @@ __global__ __launch_bounds__(256) void k_axpy_multi(double* __restrict__ w, cons
   }
 }
 
+// w = (w - sum_i coef[i] V_i) * scale, i < nv.
+template <int UNUSED = 0>
+__global__ __launch_bounds__(256) void k_axpy_scale(double* __restrict__ w, const double* __restrict__ V, int64_t stride,
+                                                    int nv, const double* __restrict__ coef, double scale, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = w[t];
+    for (int i = 0; i < nv; ++i) acc -= coef[i] * V[i * stride + t];
+    w[t] = acc * scale;
+  }
+}
+
 // out = sum_i coef[i] V_i, i < nv.
 template <int UNUSED = 0>
 __global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, const double* __restrict__ V, int64_t stride,
