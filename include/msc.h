@@ -137,7 +137,7 @@ typedef struct msc_params {
   int32_t wall_operator; /* msc_wall_operator (MSC_CORRECTOR_WALL_KINETIC) */
   double u_lid;          /* lid velocity along +x (MSC_BOUNDARY_CAVITY) */
   int32_t wall_forced;   /* Algorithm 2's forced refresh interval N_forced, 0 = off (the paper's setting) */
-  int32_t wall_restart;  /* GMRES restart length of the wall corrector, 0 = 50 */
+  int32_t wall_restart;  /* GMRES restart length of the wall corrector, 0 = 50, at most 64 */
   double krylov_tol;     /* relative residual of the wall corrector's solve, 0 = 1e-12 */
 } msc_params;
 

@@ -82,7 +82,8 @@ msc_status msc_init(const msc_params* p, const double* phat0, const double* u0, 
     return MSC_ERR_INVALID_ARG;
   }
   if (p->wall_operator != MSC_WALL_FROZEN && p->wall_operator != MSC_WALL_ADAPTIVE) return MSC_ERR_INVALID_ARG;
-  if (p->wall_forced < 0 || p->wall_restart < 0 || !(p->krylov_tol >= 0.0)) return MSC_ERR_INVALID_ARG;
+  if (p->wall_forced < 0 || p->wall_restart < 0 || p->wall_restart > 64 || !(p->krylov_tol >= 0.0))
+    return MSC_ERR_INVALID_ARG;
   if (p->extrap_states < 0 || p->extrap_states > 3) return MSC_ERR_INVALID_ARG;
   if (p->storage != MSC_STORAGE_FP64 && p->storage != MSC_STORAGE_FP32 &&
       p->storage != MSC_STORAGE_FP16_DEV)
@@ -286,11 +287,12 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
   return fwd(c, c->s->kernel_time(kind, seconds, launches, bytes_per_launch));
 }
 
-// Tuning knobs for launch-shape sweeps (not part of the documented contract):
-// key 0 = sweep tile size in sites, 1 = planes per strip, 2 = physical steps
-// enqueued per host synchronisation, 3 = speculative extra iterations,
-// 4 = graph capture of explicit chunks.  Takes effect for shapes at the next
-// call; tile and strip changes apply only before msc_init (use params).
+// Launch-shape knobs (declared in msc.h): key 0 = sweep tile size in sites,
+// 1 = planes per strip, 2 = physical steps enqueued per host synchronisation,
+// 3 = speculative extra iterations, 4 = graph capture of explicit chunks,
+// 5 = tile by table index, 6 = row transforms inside the sweep (0/1/2).
+// Keys 0, 1, 5 and 6 re-pick the launch shapes at once; the others apply
+// from the next call.
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
   if (!c) return MSC_ERR_INVALID_ARG;
   msc::Tuning& t = c->s->tuning();

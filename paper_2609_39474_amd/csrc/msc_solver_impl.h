@@ -499,10 +499,13 @@ class Solver : public SolverBase {
     wk_mu = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
     wk_mref = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
     wk_sref = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
-    wk_part = keep((double*)dalloc(sizeof(double) * kDotBlocks * (wk_m + 1)));
-    wk_coef = keep((double*)dalloc(sizeof(double) * (wk_m + 1)));
-    MSC_HIPCK(hipHostMalloc((void**)&wk_part_h, sizeof(double) * kDotBlocks * (wk_m + 1), hipHostMallocDefault));
-    MSC_HIPCK(hipHostMalloc((void**)&wk_coef_h, sizeof(double) * (wk_m + 1), hipHostMallocDefault));
+    wk_part = keep((double*)dalloc(sizeof(double) * kDotBlocks * (wk_m + 2)));
+    wk_coef = keep((double*)dalloc(sizeof(double) * (wk_m + 2)));
+    const size_t small = (size_t)wk_m * wk_m + 2 * wk_m + (wk_m + 1) + (wk_m + 2) + 1 + wk_m;
+    wk_small = keep((double*)dalloc(sizeof(double) * small));
+    MSC_HIPCK(hipHostMalloc((void**)&wk_part_h, sizeof(double) * kDotBlocks * (wk_m + 2), hipHostMallocDefault));
+    MSC_HIPCK(hipHostMalloc((void**)&wk_coef_h, sizeof(double) * (wk_m + 2), hipHostMallocDefault));
+    MSC_HIPCK(hipHostMalloc((void**)&wk_small_h, sizeof(double) * small, hipHostMallocDefault));
   }
 
   int vec_grid() const {
@@ -552,10 +555,15 @@ class Solver : public SolverBase {
       enqueue_fullsym(nullptr, 0, 0, wk_aA, nullptr, nullptr, true, true, (T*)out, (const TM*)in, 1);
   }
 
-  // Restarted GMRES(m), right-preconditioned, classical Gram-Schmidt with one
-  // re-orthogonalisation: delta ~ (I - L)^{-1} rhs to the relative residual
-  // krylov_tol.  Returns the iteration count; rel receives the final true
-  // relative residual.
+  // Restarted GMRES(m), right-preconditioned, classical Gram-Schmidt (with
+  // one re-orthogonalisation when krylov_tol < 1e-8; a single projection
+  // otherwise, which halves the passes over the basis): delta ~ (I - L)^{-1}
+  // rhs to the relative residual krylov_tol.  The orthogonalisation coefficients, the Hessenberg columns
+  // and the Givens rotations stay on the device (k_gs_first, k_gs_second);
+  // the host reads the residual estimate every kCheck iterations and the
+  // small triangular system once per cycle.  Returns the iteration count;
+  // rel receives the final true relative residual.
+  static constexpr int kCheck = 4;
   int wall_gmres(const double* rhs, double* delta, double& rel) {
     const int64_t n = (int64_t)Q * G.NS;
     const int m = wk_m;
@@ -571,64 +579,80 @@ class Solver : public SolverBase {
       rel = beta0;
       return 0;
     }
+    // device scratch of the cycle: Hd (m x m, row stride m), cs, sn, g,
+    // hcol, scale, resid
+    double* Hd = wk_small;
+    double* cs = Hd + (size_t)m * m;
+    double* sn = cs + m;
+    double* g = sn + m;
+    double* hcol = g + (m + 1);
+    double* scale = hcol + (m + 2);
+    double* resid = scale + 1;
     lincomb(wk_R, rhs, 1.0, nullptr, 0.0);
     double beta = beta0;
     int iters = 0;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 2), h2(m + 2), y(m);
+    std::vector<double> y(m);
+    const bool reorth = tol < 1e-8;
+    if (!reorth) MSC_HIPCK(hipMemsetAsync(hcol, 0, sizeof(double) * (m + 2), st));
     for (int rs = 0; rs < max_restarts; ++rs) {
       lincomb(wk_V, wk_R, 1.0 / beta, nullptr, 0.0);
-      std::fill(g.begin(), g.end(), 0.0);
-      g[0] = beta;
+      for (int i = 0; i <= m; ++i) wk_small_h[i] = (i == 0) ? beta : 0.0;
+      MSC_HIPCK(hipMemcpyAsync(g, wk_small_h, sizeof(double) * (m + 1), hipMemcpyHostToDevice, st));
       int jend = 0;
       bool done = false;
       for (int j = 0; j < m; ++j) {
         double* vj1 = wk_V + (int64_t)(j + 1) * n;
         wall_precondition(wk_V + (int64_t)j * n, wk_Z);
         wall_apply(wk_Z, vj1);
-        wall_dots(wk_V, j + 1, vj1, h.data());
-        upload_coef(h.data(), j + 1);
-        hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
-                           (const double*)wk_coef, n);
-        MSC_HIPCK(hipGetLastError());
-        // re-orthogonalisation: <V_i, w> for i <= j and <w, w> in one pass
-        // (V_{j+1} is w itself), then w <- (w - V h2)/|w - V h2| with
-        // |w - V h2|^2 = <w, w> - |h2|^2 (w - V h2 is orthogonal to V)
-        wall_dots(wk_V, j + 2, vj1, h2.data());
-        double ww = h2[j + 1], hh = 0.0;
-        for (int i = 0; i <= j; ++i) {
-          h[i] += h2[i];
-          hh += h2[i] * h2[i];
+        if (reorth) {
+          hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, (const double*)wk_V, n, j + 1,
+                             (const double*)vj1, n, wk_part);
+          hipLaunchKernelGGL(k_gs_first<0>, dim3(1), dim3(64), 0, st, (const double*)wk_part, j + 1, kDotBlocks,
+                             wk_coef, hcol);
+          hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n,
+                             j + 1, (const double*)wk_coef, n);
         }
-        const double hn = std::sqrt(std::max(ww - hh, 0.0));
-        upload_coef(h2.data(), j + 1);
+        hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, (const double*)wk_V, n, j + 2,
+                           (const double*)vj1, n, wk_part);
+        hipLaunchKernelGGL(k_gs_second<0>, dim3(1), dim3(64), 0, st, (const double*)wk_part, j, kDotBlocks, m,
+                           wk_coef, (const double*)hcol, Hd, cs, sn, g, scale, resid);
         hipLaunchKernelGGL(k_axpy_scale<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
-                           (const double*)wk_coef, hn > 0.0 ? 1.0 / hn : 1.0, n);
+                           (const double*)wk_coef, (const double*)scale, n);
         MSC_HIPCK(hipGetLastError());
-        // Givens rotations on the new column
-        for (int i = 0; i < j; ++i) {
-          const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-          h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-          h[i] = t;
-        }
-        const double den = std::hypot(h[j], hn);
-        cs[j] = den > 0.0 ? h[j] / den : 1.0;
-        sn[j] = den > 0.0 ? hn / den : 0.0;
-        h[j] = den;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
         ++iters;
         jend = j + 1;
-        if (std::fabs(g[j + 1]) <= tol * beta0 || !(hn > 0.0)) {
-          done = true;
+        if ((j + 1) % kCheck == 0 || j == m - 1) {
+          MSC_HIPCK(hipMemcpyAsync(wk_small_h, resid + j, sizeof(double), hipMemcpyDeviceToHost, st));
+          sync();
+          const double res = wk_small_h[0];
+          if (res <= tol * beta0 || !std::isfinite(res)) {
+            done = true;
+            break;
+          }
+        }
+      }
+      // y = R^{-1} g (upper triangular, jend x jend), delta += M^{-1} V y;
+      // the columns after the first converged or broken-down one are unused
+      const size_t hsz = (size_t)m * m + 2 * m + (m + 1) + (m + 2) + 1 + m;
+      MSC_HIPCK(hipMemcpyAsync(wk_small_h, Hd, sizeof(double) * hsz, hipMemcpyDeviceToHost, st));
+      sync();
+      const double* Hh = wk_small_h;
+      const double* gh = wk_small_h + (size_t)m * m + 2 * m;
+      const double* rh = gh + (m + 1) + (m + 2) + 1;
+      for (int i = 0; i < jend; ++i) {
+        if (!(std::fabs(Hh[(size_t)i * m + i]) > 0.0)) {
+          jend = i;
+          break;
+        }
+        if (rh[i] <= tol * beta0) {
+          jend = i + 1;
           break;
         }
       }
-      // y = H^{-1} g (upper triangular), delta += M^{-1} V y
       for (int i = jend - 1; i >= 0; --i) {
-        double acc = g[i];
-        for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
-        y[i] = acc / H[(size_t)i * m + i];
+        double acc = gh[i];
+        for (int k = i + 1; k < jend; ++k) acc -= Hh[(size_t)i * m + k] * y[k];
+        y[i] = acc / Hh[(size_t)i * m + i];
       }
       upload_coef(y.data(), jend);
       hipLaunchKernelGGL(k_combine<0>, dim3(vec_grid()), dim3(256), 0, st, wk_Y, (const double*)wk_V, n, jend,
@@ -964,6 +988,8 @@ class Solver : public SolverBase {
   double* wk_part_h = nullptr;
   double* wk_coef = nullptr;
   double* wk_coef_h = nullptr;
+  double* wk_small = nullptr;    // GMRES cycle bookkeeping on the device
+  double* wk_small_h = nullptr;  // its pinned host mirror
   int wk_m = 50;
   double wk_aA = 0.0;
   bool wk_rest = true;
@@ -1185,8 +1211,10 @@ class Solver : public SolverBase {
     run_flags_h = nullptr;
     if (wk_part_h) (void)hipHostFree(wk_part_h);
     if (wk_coef_h) (void)hipHostFree(wk_coef_h);
+    if (wk_small_h) (void)hipHostFree(wk_small_h);
     wk_part_h = nullptr;
     wk_coef_h = nullptr;
+    wk_small_h = nullptr;
     ctl_h = nullptr;
     stats_h = nullptr;
     partials_h = nullptr;

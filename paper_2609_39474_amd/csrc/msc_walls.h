@@ -164,15 +164,78 @@ __global__ __launch_bounds__(256) void k_axpy_multi(double* __restrict__ w, cons
   }
 }
 
-// w = (w - sum_i coef[i] V_i) * scale, i < nv.
+// w = (w - sum_i coef[i] V_i) * scale[0], i < nv (scale on the device).
 template <int UNUSED = 0>
 __global__ __launch_bounds__(256) void k_axpy_scale(double* __restrict__ w, const double* __restrict__ V, int64_t stride,
-                                                    int nv, const double* __restrict__ coef, double scale, int64_t n) {
+                                                    int nv, const double* __restrict__ coef,
+                                                    const double* __restrict__ scale, int64_t n) {
+  const double sc = scale[0];
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     double acc = w[t];
     for (int i = 0; i < nv; ++i) acc -= coef[i] * V[i * stride + t];
-    w[t] = acc * scale;
+    w[t] = acc * sc;
   }
+}
+
+// Device-side Gram-Schmidt bookkeeping of one GMRES iteration (one block;
+// sums of the dot-product partials in block order, so the result does not
+// depend on scheduling).
+//
+// k_gs_first: h = <V_i, w> for i < nv -> coef (for the projection) and hcol.
+template <int UNUSED = 0>
+__global__ __launch_bounds__(64) void k_gs_first(const double* __restrict__ partials, int nv, int nblk,
+                                                 double* __restrict__ coef, double* __restrict__ hcol) {
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += partials[(int64_t)i * nblk + b];
+    coef[i] = acc;
+    hcol[i] = acc;
+  }
+}
+
+// k_gs_second: the re-orthogonalisation coefficients h2 = <V_i, w> (i <= j)
+// and <w, w> (entry j+1) -> coef; column j of the Hessenberg matrix is
+// hcol + h2 with H(j+1, j) = |w - V h2| = sqrt(<w, w> - |h2|^2); the earlier
+// Givens rotations are applied to it, a new one zeroes H(j+1, j), g is
+// rotated; R(:, j) goes to Hd (row stride m), 1/H(j+1, j) to scale and
+// |g(j+1)| to resid[j].
+template <int UNUSED = 0>
+__global__ __launch_bounds__(64) void k_gs_second(const double* __restrict__ partials, int j, int nblk, int m,
+                                                  double* __restrict__ coef, const double* __restrict__ hcol,
+                                                  double* __restrict__ Hd, double* __restrict__ cs,
+                                                  double* __restrict__ sn, double* __restrict__ g,
+                                                  double* __restrict__ scale, double* __restrict__ resid) {
+  __shared__ double h2[72];
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += partials[(int64_t)i * nblk + b];
+    h2[i] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double hh = 0.0;
+  for (int i = 0; i <= j; ++i) hh += h2[i] * h2[i];
+  const double ww = h2[j + 1];
+  const double hn = sqrt(ww - hh > 0.0 ? ww - hh : 0.0);
+  double col[72];
+  for (int i = 0; i <= j; ++i) {
+    coef[i] = h2[i];
+    col[i] = hcol[i] + h2[i];
+  }
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], hn);
+  cs[j] = den > 0.0 ? col[j] / den : 1.0;
+  sn[j] = den > 0.0 ? hn / den : 0.0;
+  col[j] = den;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  for (int i = 0; i <= j; ++i) Hd[(int64_t)i * m + j] = col[i];
+  scale[0] = hn > 0.0 ? 1.0 / hn : 1.0;
+  resid[j] = fabs(g[j + 1]);
 }
 
 // out = sum_i coef[i] V_i, i < nv.
