@@ -186,3 +186,33 @@ def test_wall_kinetic_refusals(M):
         s.bdf2_adjoint(1, np.zeros(s.state_size()))
     assert ei.value.status == M.MSC_ERR_UNSUPPORTED
     s.close()
+
+
+def test_wall_kinetic_at_rest_stays_at_rest(M):
+    """Without the lid the zero state is the fixed point: every residual is
+    exactly zero (the solve returns df = 0 for r = 0) and the field stays 0."""
+    N = 16
+    s = _solver(M, (N, N), ulid=0.0, wall_operator="adaptive")
+    rc, stats = s.bdf2_step(3)
+    assert rc == 0 and all(x["iters"] == 1 and x["R_final"] == 0.0 for x in stats)
+    assert np.all(s.moments() == 0.0)
+    s.close()
+
+
+def test_wall_kinetic_largest_grid(M):
+    """N = 256 (the largest FP64 extent): two steps converge, every solve
+    reaches its tolerance, and the corrected count is far below Picard's."""
+    N = 256
+    ulid = 10 * NU / N
+    s = _solver(M, (N, N), ulid=ulid, dt=384.0, eps=1e-10)
+    rc, stats = s.bdf2_step(2)
+    solves, iters, _, worst = s.krylov_stats()
+    say("N=256 wall corrector counts", [x["iters"] for x in stats], "GMRES per solve", iters / max(solves, 1),
+        "worst rel residual", worst)
+    assert rc == 0 and max(x["iters"] for x in stats) <= 10
+    assert worst <= 1e-11
+    s.close()
+    p = _solver(M, (N, N), ulid=ulid, dt=384.0, eps=1e-10, corrector="picard", k_max=60)
+    rc, stats = p.bdf2_step(1, raise_on_fail=False)
+    assert rc == M.MSC_ERR_NONCONVERGED  # Picard needs far more than 60 sweeps at this step
+    p.close()
