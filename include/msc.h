@@ -321,9 +321,10 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
  * key 0), 6 = in 2D with tiles spanning whole rows, do the correction's row
  * transforms inside the sweep: 0 = neither, 1 = the forward one, 2 = the
  * forward one and, with one-plane strips, the inverse one before the lift
- * (default 2).  Results do not depend on these beyond rounding order (keys 6
- * = 1 and 2 give identical results).  MSC_ERR_INVALID_ARG for an unknown key
- * or value. */
+ * (default 2), 7 / 8 = z pencils / j_z columns per block of the 3D
+ * transform passes (0 = automatic; capped by the LDS).  Results do not
+ * depend on these beyond rounding order (keys 6 = 1 and 2 give identical
+ * results).  MSC_ERR_INVALID_ARG for an unknown key or value. */
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);
 
 #ifdef __cplusplus

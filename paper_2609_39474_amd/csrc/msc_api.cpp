@@ -290,8 +290,9 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
 // Launch-shape knobs (declared in msc.h): key 0 = sweep tile size in sites,
 // 1 = planes per strip, 2 = physical steps enqueued per host synchronisation,
 // 3 = speculative extra iterations, 4 = graph capture of explicit chunks,
-// 5 = tile by table index, 6 = row transforms inside the sweep (0/1/2).
-// Keys 0, 1, 5 and 6 re-pick the launch shapes at once; the others apply
+// 5 = tile by table index, 6 = row transforms inside the sweep (0/1/2),
+// 7 / 8 = pencils / columns per block of the 3D transform passes.
+// Keys 0, 1 and 5-8 re-pick the launch shapes at once; the others apply
 // from the next call.
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
   if (!c) return MSC_ERR_INVALID_ARG;
@@ -307,6 +308,8 @@ msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
       if (value < 0 || value > 2) return MSC_ERR_INVALID_ARG;
       t.fuse_rows = value;
       break;
+    case 7: t.fft3_pencils = value < 0 ? 0 : value; break;
+    case 8: t.fft3_cols = value < 0 ? 0 : value; break;
     default: return MSC_ERR_INVALID_ARG;
   }
   if (key <= 1 || key >= 5) return fwd(c, c->s->reconfigure());

@@ -33,6 +33,8 @@ struct Tuning {
   int fuse_rows = 2;      // 2D, tiles spanning rows: 1 = forward row transform inside the sweep,
                           // 2 = also the inverse row transform (one-plane strips)
   int sweep_tile_index = 0;  // 1-based entry of the tile table, 0 = automatic
+  int fft3_pencils = 0;      // 3D transform passes: z pencils per block, 0 = automatic
+  int fft3_cols = 0;         // 3D transform passes: j_z columns per block, 0 = automatic
 };
 
 class SolverBase {
