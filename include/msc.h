@@ -322,7 +322,10 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
  * transforms inside the sweep: 0 = neither, 1 = the forward one, 2 = the
  * forward one and, with one-plane strips, the inverse one before the lift
  * (default 2), 7 / 8 = z pencils / j_z columns per block of the 3D
- * transform passes (0 = automatic; capped by the LDS).  Results do not
+ * transform passes (0 = automatic; capped by the LDS), 9 = the full-symbol
+ * corrector's column pass as three kernels (x transforms, per-wavevector
+ * solve, inverse transforms): 0 = automatic (split from N_x = 512), 1 =
+ * split, 2 = one fused kernel.  Results do not
  * depend on these beyond rounding order (keys 6 = 1 and 2 give identical
  * results).  MSC_ERR_INVALID_ARG for an unknown key or value. */
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);

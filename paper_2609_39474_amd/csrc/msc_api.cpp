@@ -291,7 +291,8 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
 // 1 = planes per strip, 2 = physical steps enqueued per host synchronisation,
 // 3 = speculative extra iterations, 4 = graph capture of explicit chunks,
 // 5 = tile by table index, 6 = row transforms inside the sweep (0/1/2),
-// 7 / 8 = pencils / columns per block of the 3D transform passes.
+// 7 / 8 = pencils / columns per block of the 3D transform passes, 9 = the
+// full-symbol column pass split in three kernels (0 auto / 1 split / 2 fused).
 // Keys 0, 1 and 5-8 re-pick the launch shapes at once; the others apply
 // from the next call.
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
@@ -310,6 +311,10 @@ msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
       break;
     case 7: t.fft3_pencils = value < 0 ? 0 : value; break;
     case 8: t.fft3_cols = value < 0 ? 0 : value; break;
+    case 9:
+      if (value < 0 || value > 2) return MSC_ERR_INVALID_ARG;
+      t.fs_split = value;
+      break;
     default: return MSC_ERR_INVALID_ARG;
   }
   if (key <= 1 || key >= 5) return fwd(c, c->s->reconfigure());

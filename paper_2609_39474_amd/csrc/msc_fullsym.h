@@ -365,6 +365,64 @@ __global__ __launch_bounds__(256) void k_fs_cols_solve(FsArgs<T, CT, TM> A) {
   }
 }
 
+// Split form of pass 2 (more parallel at N <= 512, where one block per
+// retained column leaves most compute units idle): the x transforms of LB
+// (field, j_y) lines per block, then the solve with one wavevector per thread,
+// then the inverse x transforms.  Same arithmetic as the fused pass.
+template <class L, class T, class CT, class TM>
+__global__ __launch_bounds__(256) void k_fs_cols_fft(FsArgs<T, CT, TM> A, int sign) {
+  constexpr int Q = L::Q;
+  if (A.g.skip()) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
+  const int Nx = A.Nx, NH = A.NH, LB = A.cols_per_block;
+  cpx<CT>* tmp = buf + LB * Nx;
+  const int t0 = blockIdx.x * LB, nlines = Q * NH;
+  const int64_t FS = (int64_t)Nx * NH;
+  // line t = q * NH + j: element x at spec[q][x][j]
+  for (int i = threadIdx.x; i < LB * Nx; i += blockDim.x) {
+    const int c = i % LB, x = i / LB;
+    const int t = t0 + c;
+    cpx<CT> v = {0, 0};
+    if (t < nlines) v = A.spec[(t / NH) * FS + (int64_t)x * NH + (t % NH)];
+    buf[c * Nx + x] = v;
+  }
+  __syncthreads();
+  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgx, LB, sign, A.twx);
+  for (int i = threadIdx.x; i < LB * Nx; i += blockDim.x) {
+    const int c = i % LB, x = i / LB;
+    const int t = t0 + c;
+    if (t < nlines) A.spec[(t / NH) * FS + (int64_t)x * NH + (t % NH)] = out[c * Nx + x];
+  }
+}
+
+template <class L, class T, class CT, class TM>
+__global__ __launch_bounds__(64) void k_fs_solve_k(FsArgs<T, CT, TM> A) {
+  constexpr int Q = L::Q;
+  if (A.g.skip()) return;
+  const int Nx = A.Nx, NH = A.NH;
+  const int64_t FS = (int64_t)Nx * NH;
+  const int64_t nk = FS;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (int64_t)gridDim.x * blockDim.x) {
+    const int jx = (int)(i / NH), jy = (int)(i - (int64_t)jx * NH);
+    const double kpi[2] = {2.0 * signed_index(jx, Nx) / Nx, 2.0 * jy / A.Ny};
+    double v[Q][2];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const cpx<CT> z = A.spec[q * FS + i];
+      v[q][0] = (double)z.x;
+      v[q][1] = (double)z.y;
+    }
+    fs_solve<L>(kpi, v, A.a, A.wp, A.wm);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const cpx<CT> z = A.spec[q * FS + i];
+      const double sr = A.plain ? 0.0 : (double)z.x, si = A.plain ? 0.0 : (double)z.y;
+      A.spec[q * FS + i] = {(CT)((v[q][0] - sr) * A.inv_ns), (CT)((v[q][1] - si) * A.inv_ns)};
+    }
+  }
+}
+
 // Pass 3: inverse transform along y from the half spectrum to real rows
 // (Z(N_y - j) = conj Z(j); the j = 0 and j = N_y/2 terms of a real row are
 // real) and f <- f_T + (df - r) in place in the sweep's output buffer.

@@ -35,6 +35,8 @@ struct Tuning {
   int sweep_tile_index = 0;  // 1-based entry of the tile table, 0 = automatic
   int fft3_pencils = 0;      // 3D transform passes: z pencils per block, 0 = automatic
   int fft3_cols = 0;         // 3D transform passes: j_z columns per block, 0 = automatic
+  int fs_split = 0;          // full-symbol column pass: 0 = automatic, 1 = three kernels
+                             // (transforms, solve, transforms), 2 = one fused kernel
 };
 
 class SolverBase {

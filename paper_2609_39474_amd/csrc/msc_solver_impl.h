@@ -2018,6 +2018,9 @@ class Solver : public SolverBase {
   }
   size_t fs_rows_lds() const { return (size_t)2 * ((Q + 1) / 2) * fs_rows_per_block() * G.N2 * sizeof(cpx<CT>); }
   size_t fs_cols_lds() const { return (size_t)2 * Q * fs_cols_per_block() * G.N0 * sizeof(cpx<CT>); }
+  // split column pass: lines per block of the x transforms
+  int fs_lines_per_block() const { return std::max(1, std::min(8, 2048 / G.N0)); }
+  size_t fs_lines_lds() const { return (size_t)2 * fs_lines_per_block() * G.N0 * sizeof(cpx<CT>); }
 
   void set_fs_attrs() {
     if constexpr (D == 2 && !DV) {
@@ -2025,6 +2028,8 @@ class Solver : public SolverBase {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fs_rows_lds()));
       MSC_HIPCK(hipFuncSetAttribute((const void*)k_fs_rows_inv<L, T, CT, TM>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fs_rows_lds()));
+      MSC_HIPCK(hipFuncSetAttribute((const void*)k_fs_cols_fft<L, T, CT, TM>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)fs_lines_lds()));
       MSC_HIPCK(hipFuncSetAttribute((const void*)k_fs_cols_solve<L, T, CT, TM>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fs_cols_lds()));
     }
@@ -2070,7 +2075,22 @@ class Solver : public SolverBase {
       }
       if (tail) {
         const int cgrid = (F.NH + F.cols_per_block - 1) / F.cols_per_block;
-        hipLaunchKernelGGL((k_fs_cols_solve<L, T, CT, TM>), dim3(cgrid), dim3(256), fs_cols_lds(), st, F);
+        // split column pass where it is faster (measured: N_x = 512, 12% per
+        // iteration; at N_x <= 256 the extra launches cost more than the
+        // parallelism gains)
+        const bool split = (tune.fs_split == 1) || (tune.fs_split == 0 && G.N0 >= 512);
+        if (split) {
+          FsArgs<T, CT, TM> Fl = F;
+          Fl.cols_per_block = fs_lines_per_block();
+          const int lgrid = (Q * F.NH + Fl.cols_per_block - 1) / Fl.cols_per_block;
+          const int64_t nk = (int64_t)G.N0 * F.NH;
+          const int sgrid = (int)std::min<int64_t>((nk + 63) / 64, 4096);
+          hipLaunchKernelGGL((k_fs_cols_fft<L, T, CT, TM>), dim3(lgrid), dim3(256), fs_lines_lds(), st, Fl, -1);
+          hipLaunchKernelGGL((k_fs_solve_k<L, T, CT, TM>), dim3(sgrid), dim3(64), 0, st, F);
+          hipLaunchKernelGGL((k_fs_cols_fft<L, T, CT, TM>), dim3(lgrid), dim3(256), fs_lines_lds(), st, Fl, +1);
+        } else {
+          hipLaunchKernelGGL((k_fs_cols_solve<L, T, CT, TM>), dim3(cgrid), dim3(256), fs_cols_lds(), st, F);
+        }
         MSC_HIPCK(hipGetLastError());
         hipLaunchKernelGGL((k_fs_rows_inv<L, T, CT, TM>), dim3(rgrid), dim3(256), fs_rows_lds(), st, F);
         MSC_HIPCK(hipGetLastError());

@@ -171,3 +171,23 @@ def test_fullsym_unsupported(M):
         s.bdf2_adjoint(1, np.zeros(s.state_size()))
     assert ei.value.status == M.MSC_ERR_UNSUPPORTED
     s.close()
+
+
+@pytest.mark.parametrize("shape,storage", [((256, 256), "fp32"), ((128, 64), "fp64")])
+def test_fullsym_split_column_pass_bit_exact(M, orc, shape, storage):
+    """The column pass as three kernels (x transforms, per-wavevector solve, x
+    transforms; tuning key 9) runs the same arithmetic as the fused pass, up to
+    the compiler's choice of fused multiply-adds in each kernel."""
+    f, h = _state(orc, shape, seed=9)
+    a = 3.0 / 128.0
+    h[0] = a
+    out = []
+    for split in (2, 1):
+        s = _solver(M, shape, storage=storage, tau=(1.0, 1 / 0.7))
+        s.set_tuning(9, split)
+        fn, _, R = s.correct(f, h, a)
+        out.append((fn, R))
+        s.close()
+    tol = 1e-6 if storage == "fp32" else 1e-14
+    assert np.max(np.abs(out[0][0] - out[1][0])) <= tol * np.max(np.abs(out[0][0]))
+    assert out[0][1] == out[1][1]  # the sweep is the same kernel
