@@ -458,6 +458,9 @@ def main():
                     help="only the operating-envelope measurements (rho_obs along Lambda and nu, (Re, dt) cells)")
     ap.add_argument("--cavity", action="store_true",
                     help="only the lid-driven cavity campaign (explicit, Picard, Algorithm 2 frozen/adaptive)")
+    ap.add_argument("--cavity-cells", default="", help="cavity cells as N:Re,N:Re (default: the full set)")
+    ap.add_argument("--cavity-steps", default="", help="cavity physical step counts S, comma separated")
+    ap.add_argument("--cavity-tols", default="", help="wall corrector GMRES tolerances, comma separated")
     ap.add_argument("--fullsym", action="store_true",
                     help="only the full-symbol reference corrector: cost per iteration and off-design steps")
     ap.add_argument("--calib", action="store_true",
@@ -487,7 +490,14 @@ def main():
         print(json.dumps({"full_symbol": fullsym_cost(msc, W, stream, torch)}), flush=True)
         return
     if args.cavity:
-        print(json.dumps({"cavity": cavity_campaign(msc, stream, torch)}), flush=True)
+        kw = {}
+        if args.cavity_cells:
+            kw["cells"] = tuple((int(c.split(":")[0]), float(c.split(":")[1])) for c in args.cavity_cells.split(","))
+        if args.cavity_steps:
+            kw["S_list"] = tuple(int(v) for v in args.cavity_steps.split(","))
+        if args.cavity_tols:
+            kw["tol_list"] = tuple(float(v) for v in args.cavity_tols.split(","))
+        print(json.dumps({"cavity": cavity_campaign(msc, stream, torch, **kw)}), flush=True)
         return
     cfg = W.config(args.workload)
     N, nu, d = cfg["N"], cfg["nu"], cfg["d"]

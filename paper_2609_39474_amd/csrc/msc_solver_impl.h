@@ -608,14 +608,14 @@ class Solver : public SolverBase {
         if (reorth) {
           hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, (const double*)wk_V, n, j + 1,
                              (const double*)vj1, n, wk_part);
-          hipLaunchKernelGGL(k_gs_first<0>, dim3(1), dim3(64), 0, st, (const double*)wk_part, j + 1, kDotBlocks,
-                             wk_coef, hcol);
+          hipLaunchKernelGGL(k_gs_first<0>, dim3(1), dim3(1024), 0, st, (const double*)wk_part, j + 1, wk_coef,
+                             hcol);
           hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n,
                              j + 1, (const double*)wk_coef, n);
         }
         hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, (const double*)wk_V, n, j + 2,
                            (const double*)vj1, n, wk_part);
-        hipLaunchKernelGGL(k_gs_second<0>, dim3(1), dim3(64), 0, st, (const double*)wk_part, j, kDotBlocks, m,
+        hipLaunchKernelGGL(k_gs_second<0>, dim3(1), dim3(1024), 0, st, (const double*)wk_part, j, m,
                            wk_coef, (const double*)hcol, Hd, cs, sn, g, scale, resid);
         hipLaunchKernelGGL(k_axpy_scale<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
                            (const double*)wk_coef, (const double*)scale, n);
@@ -994,7 +994,6 @@ class Solver : public SolverBase {
   int wk_m = 50;
   double wk_aA = 0.0;
   bool wk_rest = true;
-  static constexpr int kDotBlocks = 256;
   int64_t kr_solves = 0, kr_iters = 0, kr_refresh = 0;
   double kr_worst = 0.0;
   std::vector<int32_t> wall_refreshes;

@@ -126,42 +126,140 @@ __global__ __launch_bounds__(256) void k_wall_reference(const double* __restrict
 }
 
 // ------------------------------------------------------- Krylov helpers --
+// acc[k] += <V_k, w> over this thread's elements of [b0, b1), k < G, with G
+// fixed at compile time so that the G + 1 loads of an element issue together.
+template <int G, int GMAX>
+__device__ inline void dot_rows(const double* __restrict__ v, int64_t stride, const double* __restrict__ w, int64_t b0,
+                                int64_t b1, double (&acc)[GMAX]) {
+#pragma unroll 2
+  for (int64_t t = b0 + threadIdx.x; t < b1; t += blockDim.x) {
+    const double wt = w[t];
+    double x[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) x[k] = v[k * stride + t];
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc[k] += x[k] * wt;
+  }
+}
+
+template <int G, int GMAX>
+__device__ inline void dot_rows_n(int g, const double* __restrict__ v, int64_t stride, const double* __restrict__ w,
+                                  int64_t b0, int64_t b1, double (&acc)[GMAX]) {
+  if constexpr (G > 0) {
+    if (g == G)
+      dot_rows<G, GMAX>(v, stride, w, b0, b1, acc);
+    else
+      dot_rows_n<G - 1, GMAX>(g, v, stride, w, b0, b1, acc);
+  }
+}
+
 // partials[i * gridDim.x + block] = this block's part of <V_i, w>, i < nv
-// (V_i = V + i * stride); the caller sums the partials in block order.
+// (V_i = V + i * stride).  The vectors go in groups of kDotGroup, so w is read
+// once per group and one block reduction serves the whole group.
+constexpr int kDotGroup = 16;
 template <int UNUSED = 0>
 __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int64_t stride, int nv,
                                               const double* __restrict__ w, int64_t n,
                                               double* __restrict__ partials) {
-  __shared__ double red[4];
+  __shared__ double red[kDotGroup][4];
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t b0 = (int64_t)blockIdx.x * chunk;
   const int64_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + i * stride;
-    double acc = 0.0;
-    for (int64_t t = b0 + threadIdx.x; t < b1; t += blockDim.x) acc += v[t] * w[t];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
+    const int g = (nv - i0 < kDotGroup) ? nv - i0 : kDotGroup;
+    double acc[kDotGroup];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sum = 0.0;
-      for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) sum += red[wv];
-      partials[(int64_t)i * gridDim.x + blockIdx.x] = sum;
+    for (int k = 0; k < kDotGroup; ++k) acc[k] = 0.0;
+    dot_rows_n<kDotGroup, kDotGroup>(g, V + (int64_t)i0 * stride, stride, w, b0, b1, acc);
+#pragma unroll
+    for (int k = 0; k < kDotGroup; ++k) {
+      if (k < g) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+        if (lane == 0) red[k][wv] = acc[k];
+      }
     }
     __syncthreads();
+    if ((int)threadIdx.x < g)
+      partials[(int64_t)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+          ((red[threadIdx.x][0] + red[threadIdx.x][1]) + red[threadIdx.x][2]) + red[threadIdx.x][3];
+    __syncthreads();
   }
+}
+
+// Blocks of k_dots in the Gram-Schmidt passes (a multiple of 64).
+constexpr int kDotBlocks = 512;
+
+// h[i] = sum over the kDotBlocks partials of <V_i, w>, i < nv, by the whole
+// block: wave wv takes the vectors i = wv, wv + (waves per block), ...; each
+// lane sums its kDotBlocks / 64 strided partials (loaded together), then a
+// butterfly over the wave.  The order is fixed, so the sums do not depend on
+// scheduling.
+__device__ inline void sum_partials(const double* __restrict__ partials, int nv, double* h) {
+  constexpr int kPer = kDotBlocks / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = wv; i < nv; i += (int)(blockDim.x >> 6)) {
+    const double* p = partials + (int64_t)i * kDotBlocks + lane;
+    double x[kPer];
+#pragma unroll
+    for (int b = 0; b < kPer; ++b) x[b] = p[64 * b];
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < kPer; ++b) acc += x[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) h[i] = acc;
+  }
+  __syncthreads();
+}
+
+// acc -/+= sum_k coef[k] V_k[t], k < G in order, with G fixed at compile time
+// so that the G loads of element t issue together; the _n form dispatches a
+// run-time group width g <= G.
+template <int G, bool SUB>
+__device__ inline double comb_rows(double acc, const double* __restrict__ v, int64_t stride,
+                                   const double* __restrict__ coef, int64_t t) {
+  double x[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) x[k] = v[k * stride + t];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    if constexpr (SUB)
+      acc -= coef[k] * x[k];
+    else
+      acc += coef[k] * x[k];
+  }
+  return acc;
+}
+
+template <int G, bool SUB>
+__device__ inline double comb_rows_n(int g, double acc, const double* __restrict__ v, int64_t stride,
+                                     const double* __restrict__ coef, int64_t t) {
+  if constexpr (G > 0) {
+    if (g == G) return comb_rows<G, SUB>(acc, v, stride, coef, t);
+    return comb_rows_n<G - 1, SUB>(g, acc, v, stride, coef, t);
+  } else {
+    return acc;
+  }
+}
+
+template <bool SUB>
+__device__ inline double comb_all(double acc, const double* __restrict__ V, int64_t stride, int nv,
+                                  const double* __restrict__ coef, int64_t t) {
+  for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
+    const int g = (nv - i0 < kDotGroup) ? nv - i0 : kDotGroup;
+    acc = comb_rows_n<kDotGroup, SUB>(g, acc, V + (int64_t)i0 * stride, stride, coef + i0, t);
+  }
+  return acc;
 }
 
 // w -= sum_i coef[i] V_i (coef on the device), i < nv.
 template <int UNUSED = 0>
 __global__ __launch_bounds__(256) void k_axpy_multi(double* __restrict__ w, const double* __restrict__ V, int64_t stride,
                                                     int nv, const double* __restrict__ coef, int64_t n) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    double acc = w[t];
-    for (int i = 0; i < nv; ++i) acc -= coef[i] * V[i * stride + t];
-    w[t] = acc;
-  }
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    w[t] = comb_all<true>(w[t], V, stride, nv, coef, t);
 }
 
 // w = (w - sum_i coef[i] V_i) * scale[0], i < nv (scale on the device).
@@ -170,26 +268,22 @@ __global__ __launch_bounds__(256) void k_axpy_scale(double* __restrict__ w, cons
                                                     int nv, const double* __restrict__ coef,
                                                     const double* __restrict__ scale, int64_t n) {
   const double sc = scale[0];
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    double acc = w[t];
-    for (int i = 0; i < nv; ++i) acc -= coef[i] * V[i * stride + t];
-    w[t] = acc * sc;
-  }
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    w[t] = comb_all<true>(w[t], V, stride, nv, coef, t) * sc;
 }
 
 // Device-side Gram-Schmidt bookkeeping of one GMRES iteration (one block;
-// sums of the dot-product partials in block order, so the result does not
-// depend on scheduling).
+// the dot-product partials summed by sum_partials).
 //
 // k_gs_first: h = <V_i, w> for i < nv -> coef (for the projection) and hcol.
 template <int UNUSED = 0>
-__global__ __launch_bounds__(64) void k_gs_first(const double* __restrict__ partials, int nv, int nblk,
-                                                 double* __restrict__ coef, double* __restrict__ hcol) {
+__global__ __launch_bounds__(1024) void k_gs_first(const double* __restrict__ partials, int nv,
+                                                  double* __restrict__ coef, double* __restrict__ hcol) {
+  __shared__ double h[72];
+  sum_partials(partials, nv, h);
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += partials[(int64_t)i * nblk + b];
-    coef[i] = acc;
-    hcol[i] = acc;
+    coef[i] = h[i];
+    hcol[i] = h[i];
   }
 }
 
@@ -200,53 +294,56 @@ __global__ __launch_bounds__(64) void k_gs_first(const double* __restrict__ part
 // rotated; R(:, j) goes to Hd (row stride m), 1/H(j+1, j) to scale and
 // |g(j+1)| to resid[j].
 template <int UNUSED = 0>
-__global__ __launch_bounds__(64) void k_gs_second(const double* __restrict__ partials, int j, int nblk, int m,
-                                                  double* __restrict__ coef, const double* __restrict__ hcol,
-                                                  double* __restrict__ Hd, double* __restrict__ cs,
-                                                  double* __restrict__ sn, double* __restrict__ g,
-                                                  double* __restrict__ scale, double* __restrict__ resid) {
-  __shared__ double h2[72];
-  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += partials[(int64_t)i * nblk + b];
-    h2[i] = acc;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double hh = 0.0;
-  for (int i = 0; i <= j; ++i) hh += h2[i] * h2[i];
-  const double ww = h2[j + 1];
-  const double hn = sqrt(ww - hh > 0.0 ? ww - hh : 0.0);
-  double col[72];
-  for (int i = 0; i <= j; ++i) {
+__global__ __launch_bounds__(1024) void k_gs_second(const double* __restrict__ partials, int j, int m,
+                                                   double* __restrict__ coef, const double* __restrict__ hcol,
+                                                   double* __restrict__ Hd, double* __restrict__ cs,
+                                                   double* __restrict__ sn, double* __restrict__ g,
+                                                   double* __restrict__ scale, double* __restrict__ resid) {
+  __shared__ double h2[72], col[72], c_s[72], s_s[72];
+  sum_partials(partials, j + 2, h2);
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
     coef[i] = h2[i];
     col[i] = hcol[i] + h2[i];
+    if (i < j) {
+      c_s[i] = cs[i];
+      s_s[i] = sn[i];
+    }
   }
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double hh = 0.0;
+    for (int i = 0; i <= j; ++i) hh += h2[i] * h2[i];
+    const double ww = h2[j + 1];
+    const double hn = sqrt(ww - hh > 0.0 ? ww - hh : 0.0);
+    // the earlier rotations; the running entry stays in a register
+    double cur = col[0];
+    for (int i = 0; i < j; ++i) {
+      const double nxt = col[i + 1];
+      col[i] = c_s[i] * cur + s_s[i] * nxt;
+      cur = -s_s[i] * cur + c_s[i] * nxt;
+    }
+    const double den = hypot(cur, hn);
+    const double cj = den > 0.0 ? cur / den : 1.0;
+    const double sj = den > 0.0 ? hn / den : 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    col[j] = den;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = cj * gj;
+    scale[0] = hn > 0.0 ? 1.0 / hn : 1.0;
+    resid[j] = fabs(sj * gj);
   }
-  const double den = hypot(col[j], hn);
-  cs[j] = den > 0.0 ? col[j] / den : 1.0;
-  sn[j] = den > 0.0 ? hn / den : 0.0;
-  col[j] = den;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  for (int i = 0; i <= j; ++i) Hd[(int64_t)i * m + j] = col[i];
-  scale[0] = hn > 0.0 ? 1.0 / hn : 1.0;
-  resid[j] = fabs(g[j + 1]);
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) Hd[(int64_t)i * m + j] = col[i];
 }
 
 // out = sum_i coef[i] V_i, i < nv.
 template <int UNUSED = 0>
 __global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, const double* __restrict__ V, int64_t stride,
                                                  int nv, const double* __restrict__ coef, int64_t n) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int i = 0; i < nv; ++i) acc += coef[i] * V[i * stride + t];
-    out[t] = acc;
-  }
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = comb_all<false>(0.0, V, stride, nv, coef, t);
 }
 
 // out = alpha * x + beta * y (any of x, y may alias out).
