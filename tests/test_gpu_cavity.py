@@ -216,3 +216,38 @@ def test_wall_kinetic_largest_grid(M):
     rc, stats = p.bdf2_step(1, raise_on_fail=False)
     assert rc == M.MSC_ERR_NONCONVERGED  # Picard needs far more than 60 sweeps at this step
     p.close()
+
+
+@pytest.mark.parametrize("restart,tol", [(6, 1e-10), (50, 1e-2), (50, 1e-4)])
+def test_wall_gmres_restarts_and_loose_tolerance(M, orc, restart, tol):
+    """Short restarts (many cycles) and the loose tolerances (one projection
+    per Gram-Schmidt step): the returned correction d satisfies
+    |(I - L) d - r| <= tol |r| against the oracle's assembled L, and the
+    library's reported final residual is that same number."""
+    import scipy.sparse as sp
+    shape = (32, 32)
+    ulid = 0.04
+    dt = 32.0
+    f, h = _state(orc, shape, seed=11)
+    a = 1.0 / dt
+    p = M.make_params(2, shape[0], dt=dt, eps=1e-10, storage="fp64", corrector="wall_kinetic", n_min=1, k_max=600,
+                      boundary="cavity", u_lid=ulid, wall_restart=restart, krylov_tol=tol)
+    s = M.Solver(p, np.zeros(shape), np.zeros((2,) + shape))
+    fn, _, _ = s.correct(f, h, a)
+    a2 = 1.5 / dt
+    mref = np.zeros((3,) + shape)
+    mref[0] = 1.0
+    L = orc.cavity_operator(orc.cavity_local_jacobians(mref, np.zeros_like(mref), a2), shape)
+    fT, _ = orc.cavity_sweep(f, h, a, ulid)
+    r = (fT - f).ravel()
+    d = (fn - f).ravel()
+    res = (sp.identity(L.shape[0], format="csr") - L) @ d - r
+    rel = float(np.linalg.norm(res) / np.linalg.norm(r))
+    solves, iters, _, worst = s.krylov_stats()
+    say("GMRES restart", restart, "tol", tol, "iterations", iters, "true rel residual", rel, "reported", worst)
+    assert solves == 1 and iters >= 1
+    assert rel <= tol * (1.0 + 1e-6)
+    assert abs(rel - worst) <= 1e-9 + 1e-6 * rel
+    if restart < iters:
+        assert iters > restart  # more than one cycle ran
+    s.close()
