@@ -169,15 +169,19 @@ __global__ __launch_bounds__(256) void k_fft2_cols_solve(Fft2Args<CT, TM> A, Acc
                            (int64_t)gridDim.x * blockDim.x);
       return;
     }
-    if ((int)blockIdx.x * A.cols_per_block >= A.NBy) return;  // reconstruction-only block
   } else if (A.g.skip()) {
     return;
   }
+  // XCD-aware column order over the first pad8(column blocks) blocks; the
+  // rest (decision mode) only reconstruct
+  const int Nx = A.Nx, JB = A.cols_per_block, NB = A.NBy;
+  const int GC = pad8((NB + JB - 1) / JB);
+  const int cbk = ((int)blockIdx.x < GC) ? xcd_item(blockIdx.x, GC) : (int)blockIdx.x;
+  if (cbk * JB >= NB) return;  // padding or reconstruction-only block
   extern __shared__ unsigned char smem_raw[];
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
-  const int Nx = A.Nx, JB = A.cols_per_block, NB = A.NBy;
   cpx<CT>* tmp = buf + 3 * JB * Nx;
-  const int j0 = blockIdx.x * JB;
+  const int j0 = cbk * JB;
   const int64_t FS = (int64_t)Nx * NB;
   // transform t = f*JB + c holds column j0 + c of field f
   for (int i = threadIdx.x; i < 3 * JB * Nx; i += blockDim.x) {
@@ -356,7 +360,9 @@ __global__ __launch_bounds__(256) void k_fft3_y_fwd(Fft3Args<CT, TM> A) {
   const int Ny = A.Ny, JB = A.cols_per_block, NBz = A.NBz;
   cpx<CT>* tmp = buf + 4 * JB * Ny;
   const int ngroups = (NBz + JB - 1) / JB;
-  const int x = blockIdx.x / ngroups, j0 = (blockIdx.x % ngroups) * JB;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= A.Nx * ngroups) return;  // grid padding
+  const int x = item / ngroups, j0 = (item % ngroups) * JB;
   const int64_t FS1 = (int64_t)A.Nx * Ny * NBz, FS2 = (int64_t)A.Nx * A.NBy * NBz;
   for (int i = threadIdx.x; i < 4 * JB * Ny; i += blockDim.x) {
     const int c = i % JB, rest = i / JB;
@@ -385,7 +391,9 @@ __global__ __launch_bounds__(256) void k_fft3_x_solve(Fft3Args<CT, TM> A) {
   const int Nx = A.Nx, JB = A.cols_per_block, NBz = A.NBz, NBy = A.NBy;
   cpx<CT>* tmp = buf + 4 * JB * Nx;
   const int ngroups = (NBz + JB - 1) / JB;
-  const int bi = blockIdx.x / ngroups, j0 = (blockIdx.x % ngroups) * JB;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= NBy * ngroups) return;  // grid padding
+  const int bi = item / ngroups, j0 = (item % ngroups) * JB;
   const int64_t FS2 = (int64_t)Nx * NBy * NBz;
   for (int i = threadIdx.x; i < 4 * JB * Nx; i += blockDim.x) {
     const int c = i % JB, rest = i / JB;
@@ -438,7 +446,9 @@ __global__ __launch_bounds__(256) void k_fft3_y_inv(Fft3Args<CT, TM> A) {
   const int Ny = A.Ny, JB = A.cols_per_block, NBz = A.NBz, NBy = A.NBy;
   cpx<CT>* tmp = buf + 4 * JB * Ny;
   const int ngroups = (NBz + JB - 1) / JB;
-  const int x = blockIdx.x / ngroups, j0 = (blockIdx.x % ngroups) * JB;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= A.Nx * ngroups) return;  // grid padding
+  const int x = item / ngroups, j0 = (item % ngroups) * JB;
   const int64_t FS1 = (int64_t)A.Nx * Ny * NBz, FS2 = (int64_t)A.Nx * NBy * NBz;
   for (int i = threadIdx.x; i < 4 * JB * Ny; i += blockDim.x) {
     const int c = i % JB, rest = i / JB;

@@ -315,7 +315,9 @@ __global__ __launch_bounds__(256) void k_fs_cols_solve(FsArgs<T, CT, TM> A) {
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
   const int Nx = A.Nx, JB = A.cols_per_block, NH = A.NH;
   cpx<CT>* tmp = buf + Q * JB * Nx;
-  const int j0 = blockIdx.x * JB;
+  const int cbk = xcd_item(blockIdx.x, gridDim.x);
+  if (cbk * JB >= NH) return;  // grid padding
+  const int j0 = cbk * JB;
   const int64_t FS = (int64_t)Nx * NH;
   // transform t = q*JB + c holds column j0 + c of field q
   for (int i = threadIdx.x; i < Q * JB * Nx; i += blockDim.x) {
@@ -377,7 +379,8 @@ __global__ __launch_bounds__(256) void k_fs_cols_fft(FsArgs<T, CT, TM> A, int si
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
   const int Nx = A.Nx, NH = A.NH, LB = A.cols_per_block;
   cpx<CT>* tmp = buf + LB * Nx;
-  const int t0 = blockIdx.x * LB, nlines = Q * NH;
+  const int t0 = xcd_item(blockIdx.x, gridDim.x) * LB, nlines = Q * NH;
+  if (t0 >= nlines) return;  // grid padding
   const int64_t FS = (int64_t)Nx * NH;
   // line t = q * NH + j: element x at spec[q][x][j]
   for (int i = threadIdx.x; i < LB * Nx; i += blockDim.x) {

@@ -30,6 +30,13 @@ __device__ __forceinline__ cpx<CT> cmuli(cpx<CT> a, int s) {
   return s > 0 ? cpx<CT>{-a.y, a.x} : cpx<CT>{a.y, -a.x};
 }
 
+// XCD-aware order of the column passes: a grid of G blocks, G a multiple of 8
+// (the host pads it), is dealt to the 8 XCDs round-robin; block b takes work
+// item (b mod 8) G/8 + b/8, so that each XCD gets a contiguous range of items
+// (adjacent columns, whose values share cache lines) and its L2 serves them.
+__device__ __forceinline__ int xcd_item(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
+__host__ __device__ constexpr int pad8(int n) { return (n + 7) / 8 * 8; }
+
 // nt independent transforms of length N = 2^lg stored contiguously at
 // buf + t*N.  sign = -1 forward, +1 inverse (no scaling).  The caller has
 // synchronised after filling buf; returns the array holding the result (buf

@@ -2073,7 +2073,7 @@ class Solver : public SolverBase {
         MSC_HIPCK(hipGetLastError());
       }
       if (tail) {
-        const int cgrid = (F.NH + F.cols_per_block - 1) / F.cols_per_block;
+        const int cgrid = pad8((F.NH + F.cols_per_block - 1) / F.cols_per_block);  // XCD-aware order
         // split column pass where it is faster (measured: N_x = 512, 12% per
         // iteration; at N_x <= 256 the extra launches cost more than the
         // parallelism gains)
@@ -2081,7 +2081,7 @@ class Solver : public SolverBase {
         if (split) {
           FsArgs<T, CT, TM> Fl = F;
           Fl.cols_per_block = fs_lines_per_block();
-          const int lgrid = (Q * F.NH + Fl.cols_per_block - 1) / Fl.cols_per_block;
+          const int lgrid = pad8((Q * F.NH + Fl.cols_per_block - 1) / Fl.cols_per_block);
           const int64_t nk = (int64_t)G.N0 * F.NH;
           const int sgrid = (int)std::min<int64_t>((nk + 63) / 64, 4096);
           hipLaunchKernelGGL((k_fs_cols_fft<L, T, CT, TM>), dim3(lgrid), dim3(256), fs_lines_lds(), st, Fl, -1);
@@ -2139,7 +2139,8 @@ class Solver : public SolverBase {
       const size_t rows_b = 4 * (size_t)F.rows_per_block * G.N2 * cb;
       const size_t cols_b = 6 * (size_t)F.cols_per_block * G.N0 * cb;
       const int grows = G.N0 / F.rows_per_block;
-      const int gcols = (F.NBy + F.cols_per_block - 1) / F.cols_per_block;
+      // column blocks rounded up to a multiple of 8 (the XCD-aware order)
+      const int gcols = pad8((F.NBy + F.cols_per_block - 1) / F.cols_per_block);
       if (rows_in_sweep) {
         // the sweep wrote the row spectrum; the column pass decides
         F.do_accept = 0;
@@ -2206,11 +2207,11 @@ class Solver : public SolverBase {
         MSC_HIPCK(hipGetLastError());
       }
       if (!tail) return;
-      hipLaunchKernelGGL((k_fft3_y_fwd<CX, TX>), dim3(F.Nx * ng), dim3(256), yb, st, F);
+      hipLaunchKernelGGL((k_fft3_y_fwd<CX, TX>), dim3(pad8(F.Nx * ng)), dim3(256), yb, st, F);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft3_x_solve<CX, TX>), dim3(F.NBy * ng), dim3(256), xb, st, F);
+      hipLaunchKernelGGL((k_fft3_x_solve<CX, TX>), dim3(pad8(F.NBy * ng)), dim3(256), xb, st, F);
       MSC_HIPCK(hipGetLastError());
-      hipLaunchKernelGGL((k_fft3_y_inv<CX, TX>), dim3(F.Nx * ng), dim3(256), yb, st, F);
+      hipLaunchKernelGGL((k_fft3_y_inv<CX, TX>), dim3(pad8(F.Nx * ng)), dim3(256), yb, st, F);
       MSC_HIPCK(hipGetLastError());
       hipLaunchKernelGGL((k_fft3_z_inv<CX, TX>), dim3(gz), dim3(256), zb, st, F);
       MSC_HIPCK(hipGetLastError());
