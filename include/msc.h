@@ -49,7 +49,7 @@ typedef enum msc_status {
   MSC_ERR_STATE = 4,         /* context unusable after an earlier device error */
   MSC_ERR_NONCONVERGED = 5,  /* K_max inner iterations without acceptance (Alg. 1, last line) */
   MSC_ERR_NONFINITE = 6,     /* a non-finite raw residual (never accepted, Sec. 4.1) */
-  MSC_ERR_UNSUPPORTED = 7    /* valid request this build does not implement */
+  MSC_ERR_UNSUPPORTED = 7    /* valid request the library does not implement */
 } msc_status;
 
 typedef enum msc_lattice { MSC_D2Q9 = 2, MSC_D3Q19 = 3 } msc_lattice;

@@ -180,7 +180,7 @@ const char* msc_status_string(msc_status s) {
     case MSC_ERR_STATE: return "context unusable after an earlier device error";
     case MSC_ERR_NONCONVERGED: return "inner iteration reached K_max without acceptance";
     case MSC_ERR_NONFINITE: return "non-finite raw residual";
-    case MSC_ERR_UNSUPPORTED: return "not supported by this build";
+    case MSC_ERR_UNSUPPORTED: return "not supported by this library";
   }
   return "unknown status";
 }
