@@ -497,6 +497,8 @@ class Solver : public SolverBase {
     wk_Y = keep((double*)dalloc(sizeof(double) * n));
     wk_Z = keep((double*)dalloc(sizeof(double) * n));
     wk_D = keep((double*)dalloc(sizeof(double) * n));
+    wk_W = keep((double*)dalloc(sizeof(double) * n));
+    wk_vc = keep((double*)dalloc(sizeof(double) * n));
     wk_mu = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
     wk_mref = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
     wk_sref = keep((double*)dalloc(sizeof(double) * 3 * G.NS));
@@ -517,7 +519,7 @@ class Solver : public SolverBase {
   // <V_i, w> for i < nv, summed on the host in block order
   void wall_dots(const double* V, int nv, const double* w, double* out) {
     const int64_t n = (int64_t)Q * G.NS;
-    hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, V, n, nv, w, n, wk_part);
+    hipLaunchKernelGGL(k_dots<double>, dim3(kDotBlocks), dim3(256), 0, st, V, n, nv, w, n, wk_part, 0);
     MSC_HIPCK(hipGetLastError());
     MSC_HIPCK(hipMemcpyAsync(wk_part_h, wk_part, sizeof(double) * kDotBlocks * nv, hipMemcpyDeviceToHost, st));
     sync();
@@ -559,17 +561,28 @@ class Solver : public SolverBase {
   // Restarted GMRES(m), right-preconditioned, classical Gram-Schmidt (with
   // one re-orthogonalisation when krylov_tol < 1e-8; a single projection
   // otherwise, which halves the passes over the basis): delta ~ (I - L)^{-1}
-  // rhs to the relative residual krylov_tol.  The orthogonalisation coefficients, the Hessenberg columns
-  // and the Givens rotations stay on the device (k_gs_first, k_gs_second);
-  // the host reads the residual estimate every kCheck iterations and the
-  // small triangular system once per cycle.  Returns the iteration count;
-  // rel receives the final true relative residual.
+  // rhs to the relative residual krylov_tol.  The basis is stored in FP32 when
+  // krylov_tol >= 1e-5 (half the bytes of the passes over it; its rounding,
+  // ~1e-7 relative, stays far below such tolerances), else in FP64; the new
+  // vector, the coefficients and every sum are FP64.  The orthogonalisation
+  // coefficients, the Hessenberg columns and the Givens rotations stay on the
+  // device (k_gs_first, k_gs_second); the host reads the residual estimate
+  // every kCheck iterations and the small triangular system once per cycle.
+  // Returns the iteration count; rel receives the final true relative
+  // residual.
   static constexpr int kCheck = 4;
   int wall_gmres(const double* rhs, double* delta, double& rel) {
+    const double tol = P.krylov_tol > 0.0 ? P.krylov_tol : 1e-12;
+    return tol >= 1e-5 ? wall_gmres_t<float>(rhs, delta, rel) : wall_gmres_t<double>(rhs, delta, rel);
+  }
+
+  template <class VT>
+  int wall_gmres_t(const double* rhs, double* delta, double& rel) {
     const int64_t n = (int64_t)Q * G.NS;
     const int m = wk_m;
     const double tol = P.krylov_tol > 0.0 ? P.krylov_tol : 1e-12;
     const int max_restarts = 40;
+    VT* V = reinterpret_cast<VT*>(wk_V);
     double b2 = 0.0;
     wall_dots(rhs, 1, rhs, &b2);
     const double beta0 = std::sqrt(b2);
@@ -596,29 +609,32 @@ class Solver : public SolverBase {
     const bool reorth = tol < 1e-8;
     if (!reorth) MSC_HIPCK(hipMemsetAsync(hcol, 0, sizeof(double) * (m + 2), st));
     for (int rs = 0; rs < max_restarts; ++rs) {
-      lincomb(wk_V, wk_R, 1.0 / beta, nullptr, 0.0);
+      hipLaunchKernelGGL(k_scale_to<VT>, dim3(vec_grid()), dim3(256), 0, st, V, wk_vc, (const double*)wk_R,
+                         1.0 / beta, n);
+      MSC_HIPCK(hipGetLastError());
       for (int i = 0; i <= m; ++i) wk_small_h[i] = (i == 0) ? beta : 0.0;
       MSC_HIPCK(hipMemcpyAsync(g, wk_small_h, sizeof(double) * (m + 1), hipMemcpyHostToDevice, st));
       int jend = 0;
       bool done = false;
       for (int j = 0; j < m; ++j) {
-        double* vj1 = wk_V + (int64_t)(j + 1) * n;
-        wall_precondition(wk_V + (int64_t)j * n, wk_Z);
-        wall_apply(wk_Z, vj1);
+        VT* vj1 = V + (int64_t)(j + 1) * n;
+        // w = (I - L) M^{-1} v_j, from the FP64 copy of v_j
+        wall_precondition(wk_vc, wk_Z);
+        wall_apply(wk_Z, wk_W);
         if (reorth) {
-          hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, (const double*)wk_V, n, j + 1,
-                             (const double*)vj1, n, wk_part);
+          hipLaunchKernelGGL(k_dots<VT>, dim3(kDotBlocks), dim3(256), 0, st, (const VT*)V, n, j + 1,
+                             (const double*)wk_W, n, wk_part, 0);
           hipLaunchKernelGGL(k_gs_first<0>, dim3(1), dim3(1024), 0, st, (const double*)wk_part, j + 1, wk_coef,
                              hcol);
-          hipLaunchKernelGGL(k_axpy_multi<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n,
-                             j + 1, (const double*)wk_coef, n);
+          hipLaunchKernelGGL(k_axpy_multi<VT>, dim3(vec_grid()), dim3(256), 0, st, wk_W, (const VT*)V, n, j + 1,
+                             (const double*)wk_coef, n);
         }
-        hipLaunchKernelGGL(k_dots<0>, dim3(kDotBlocks), dim3(256), 0, st, (const double*)wk_V, n, j + 2,
-                           (const double*)vj1, n, wk_part);
+        hipLaunchKernelGGL(k_dots<VT>, dim3(kDotBlocks), dim3(256), 0, st, (const VT*)V, n, j + 1,
+                           (const double*)wk_W, n, wk_part, 1);
         hipLaunchKernelGGL(k_gs_second<0>, dim3(1), dim3(1024), 0, st, (const double*)wk_part, j, m,
                            wk_coef, (const double*)hcol, Hd, cs, sn, g, scale, resid);
-        hipLaunchKernelGGL(k_axpy_scale<0>, dim3(vec_grid()), dim3(256), 0, st, vj1, (const double*)wk_V, n, j + 1,
-                           (const double*)wk_coef, (const double*)scale, n);
+        hipLaunchKernelGGL(k_axpy_scale<VT>, dim3(vec_grid()), dim3(256), 0, st, vj1, wk_vc, (const double*)wk_W,
+                           (const VT*)V, n, j + 1, (const double*)wk_coef, (const double*)scale, n);
         MSC_HIPCK(hipGetLastError());
         ++iters;
         jend = j + 1;
@@ -656,7 +672,7 @@ class Solver : public SolverBase {
         y[i] = acc / Hh[(size_t)i * m + i];
       }
       upload_coef(y.data(), jend);
-      hipLaunchKernelGGL(k_combine<0>, dim3(vec_grid()), dim3(256), 0, st, wk_Y, (const double*)wk_V, n, jend,
+      hipLaunchKernelGGL(k_combine<VT>, dim3(vec_grid()), dim3(256), 0, st, wk_Y, (const VT*)V, n, jend,
                          (const double*)wk_coef, n);
       MSC_HIPCK(hipGetLastError());
       wall_precondition(wk_Y, wk_Z);
@@ -982,6 +998,8 @@ class Solver : public SolverBase {
   double* wk_Y = nullptr;
   double* wk_Z = nullptr;
   double* wk_D = nullptr;
+  double* wk_W = nullptr;   // the new Krylov vector before its orthogonalisation
+  double* wk_vc = nullptr;  // FP64 copy of the newest basis vector (preconditioner input)
   double* wk_mu = nullptr;
   double* wk_mref = nullptr;
   double* wk_sref = nullptr;

@@ -126,41 +126,55 @@ __global__ __launch_bounds__(256) void k_wall_reference(const double* __restrict
 }
 
 // ------------------------------------------------------- Krylov helpers --
+// The Krylov basis V is stored in VT: double, or float for the loose
+// tolerances (the new vector w, the coefficients and every sum stay FP64).
+//
 // acc[k] += <V_k, w> over this thread's elements of [b0, b1), k < G, with G
 // fixed at compile time so that the G + 1 loads of an element issue together.
-template <int G, int GMAX>
-__device__ inline void dot_rows(const double* __restrict__ v, int64_t stride, const double* __restrict__ w, int64_t b0,
+template <int G, int GMAX, class VT>
+__device__ inline void dot_rows(const VT* __restrict__ v, int64_t stride, const double* __restrict__ w, int64_t b0,
                                 int64_t b1, double (&acc)[GMAX]) {
 #pragma unroll 2
   for (int64_t t = b0 + threadIdx.x; t < b1; t += blockDim.x) {
     const double wt = w[t];
     double x[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) x[k] = v[k * stride + t];
+    for (int k = 0; k < G; ++k) x[k] = (double)v[k * stride + t];
 #pragma unroll
     for (int k = 0; k < G; ++k) acc[k] += x[k] * wt;
   }
 }
 
-template <int G, int GMAX>
-__device__ inline void dot_rows_n(int g, const double* __restrict__ v, int64_t stride, const double* __restrict__ w,
+template <int G, int GMAX, class VT>
+__device__ inline void dot_rows_n(int g, const VT* __restrict__ v, int64_t stride, const double* __restrict__ w,
                                   int64_t b0, int64_t b1, double (&acc)[GMAX]) {
   if constexpr (G > 0) {
     if (g == G)
-      dot_rows<G, GMAX>(v, stride, w, b0, b1, acc);
+      dot_rows<G, GMAX, VT>(v, stride, w, b0, b1, acc);
     else
-      dot_rows_n<G - 1, GMAX>(g, v, stride, w, b0, b1, acc);
+      dot_rows_n<G - 1, GMAX, VT>(g, v, stride, w, b0, b1, acc);
   }
 }
 
 // partials[i * gridDim.x + block] = this block's part of <V_i, w>, i < nv
-// (V_i = V + i * stride).  The vectors go in groups of kDotGroup, so w is read
-// once per group and one block reduction serves the whole group.
+// (V_i = V + i * stride), and with self also <w, w> at i = nv.  The vectors go
+// in groups of kDotGroup, so w is read once per group and one block reduction
+// serves the whole group.
 constexpr int kDotGroup = 16;
-template <int UNUSED = 0>
-__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int64_t stride, int nv,
+__device__ inline void block_sum_store(double acc, double* red4, double* dst) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) red4[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *dst = ((red4[0] + red4[1]) + red4[2]) + red4[3];
+  __syncthreads();
+}
+
+template <class VT>
+__global__ __launch_bounds__(256) void k_dots(const VT* __restrict__ V, int64_t stride, int nv,
                                               const double* __restrict__ w, int64_t n,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials, int self) {
   __shared__ double red[kDotGroup][4];
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t b0 = (int64_t)blockIdx.x * chunk;
@@ -171,7 +185,7 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int6
     double acc[kDotGroup];
 #pragma unroll
     for (int k = 0; k < kDotGroup; ++k) acc[k] = 0.0;
-    dot_rows_n<kDotGroup, kDotGroup>(g, V + (int64_t)i0 * stride, stride, w, b0, b1, acc);
+    dot_rows_n<kDotGroup, kDotGroup, VT>(g, V + (int64_t)i0 * stride, stride, w, b0, b1, acc);
 #pragma unroll
     for (int k = 0; k < kDotGroup; ++k) {
       if (k < g) {
@@ -185,6 +199,11 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int6
       partials[(int64_t)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] =
           ((red[threadIdx.x][0] + red[threadIdx.x][1]) + red[threadIdx.x][2]) + red[threadIdx.x][3];
     __syncthreads();
+  }
+  if (self) {
+    double acc = 0.0;
+    for (int64_t t = b0 + threadIdx.x; t < b1; t += blockDim.x) acc += w[t] * w[t];
+    block_sum_store(acc, red[0], &partials[(int64_t)nv * gridDim.x + blockIdx.x]);
   }
 }
 
@@ -217,12 +236,12 @@ __device__ inline void sum_partials(const double* __restrict__ partials, int nv,
 // acc -/+= sum_k coef[k] V_k[t], k < G in order, with G fixed at compile time
 // so that the G loads of element t issue together; the _n form dispatches a
 // run-time group width g <= G.
-template <int G, bool SUB>
-__device__ inline double comb_rows(double acc, const double* __restrict__ v, int64_t stride,
+template <int G, bool SUB, class VT>
+__device__ inline double comb_rows(double acc, const VT* __restrict__ v, int64_t stride,
                                    const double* __restrict__ coef, int64_t t) {
   double x[G];
 #pragma unroll
-  for (int k = 0; k < G; ++k) x[k] = v[k * stride + t];
+  for (int k = 0; k < G; ++k) x[k] = (double)v[k * stride + t];
 #pragma unroll
   for (int k = 0; k < G; ++k) {
     if constexpr (SUB)
@@ -233,43 +252,60 @@ __device__ inline double comb_rows(double acc, const double* __restrict__ v, int
   return acc;
 }
 
-template <int G, bool SUB>
-__device__ inline double comb_rows_n(int g, double acc, const double* __restrict__ v, int64_t stride,
+template <int G, bool SUB, class VT>
+__device__ inline double comb_rows_n(int g, double acc, const VT* __restrict__ v, int64_t stride,
                                      const double* __restrict__ coef, int64_t t) {
   if constexpr (G > 0) {
-    if (g == G) return comb_rows<G, SUB>(acc, v, stride, coef, t);
-    return comb_rows_n<G - 1, SUB>(g, acc, v, stride, coef, t);
+    if (g == G) return comb_rows<G, SUB, VT>(acc, v, stride, coef, t);
+    return comb_rows_n<G - 1, SUB, VT>(g, acc, v, stride, coef, t);
   } else {
     return acc;
   }
 }
 
-template <bool SUB>
-__device__ inline double comb_all(double acc, const double* __restrict__ V, int64_t stride, int nv,
+template <bool SUB, class VT>
+__device__ inline double comb_all(double acc, const VT* __restrict__ V, int64_t stride, int nv,
                                   const double* __restrict__ coef, int64_t t) {
   for (int i0 = 0; i0 < nv; i0 += kDotGroup) {
     const int g = (nv - i0 < kDotGroup) ? nv - i0 : kDotGroup;
-    acc = comb_rows_n<kDotGroup, SUB>(g, acc, V + (int64_t)i0 * stride, stride, coef + i0, t);
+    acc = comb_rows_n<kDotGroup, SUB, VT>(g, acc, V + (int64_t)i0 * stride, stride, coef + i0, t);
   }
   return acc;
 }
 
 // w -= sum_i coef[i] V_i (coef on the device), i < nv.
-template <int UNUSED = 0>
-__global__ __launch_bounds__(256) void k_axpy_multi(double* __restrict__ w, const double* __restrict__ V, int64_t stride,
+template <class VT>
+__global__ __launch_bounds__(256) void k_axpy_multi(double* __restrict__ w, const VT* __restrict__ V, int64_t stride,
                                                     int nv, const double* __restrict__ coef, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    w[t] = comb_all<true>(w[t], V, stride, nv, coef, t);
+    w[t] = comb_all<true, VT>(w[t], V, stride, nv, coef, t);
 }
 
-// w = (w - sum_i coef[i] V_i) * scale[0], i < nv (scale on the device).
-template <int UNUSED = 0>
-__global__ __launch_bounds__(256) void k_axpy_scale(double* __restrict__ w, const double* __restrict__ V, int64_t stride,
-                                                    int nv, const double* __restrict__ coef,
+// the next basis vector: v = (w - sum_i coef[i] V_i) * scale[0], i < nv (coef
+// and scale on the device), into out (VT) and its FP64 copy out64 (the
+// preconditioner's next input), unless out64 is null.
+template <class VT>
+__global__ __launch_bounds__(256) void k_axpy_scale(VT* __restrict__ out, double* __restrict__ out64,
+                                                    const double* __restrict__ w, const VT* __restrict__ V,
+                                                    int64_t stride, int nv, const double* __restrict__ coef,
                                                     const double* __restrict__ scale, int64_t n) {
   const double sc = scale[0];
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    w[t] = comb_all<true>(w[t], V, stride, nv, coef, t) * sc;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double v = comb_all<true, VT>(w[t], V, stride, nv, coef, t) * sc;
+    out[t] = (VT)v;
+    if (out64) out64[t] = v;
+  }
+}
+
+// out = alpha x into the basis type (and its FP64 copy out64 unless null).
+template <class VT>
+__global__ __launch_bounds__(256) void k_scale_to(VT* __restrict__ out, double* __restrict__ out64,
+                                                  const double* __restrict__ x, double alpha, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double v = alpha * x[t];
+    out[t] = (VT)v;
+    if (out64) out64[t] = v;
+  }
 }
 
 // Device-side Gram-Schmidt bookkeeping of one GMRES iteration (one block;
@@ -339,11 +375,11 @@ __global__ __launch_bounds__(1024) void k_gs_second(const double* __restrict__ p
 }
 
 // out = sum_i coef[i] V_i, i < nv.
-template <int UNUSED = 0>
-__global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, const double* __restrict__ V, int64_t stride,
+template <class VT>
+__global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, const VT* __restrict__ V, int64_t stride,
                                                  int nv, const double* __restrict__ coef, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    out[t] = comb_all<false>(0.0, V, stride, nv, coef, t);
+    out[t] = comb_all<false, VT>(0.0, V, stride, nv, coef, t);
 }
 
 // out = alpha * x + beta * y (any of x, y may alias out).
