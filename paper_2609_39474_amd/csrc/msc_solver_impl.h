@@ -1663,11 +1663,21 @@ class Solver : public SolverBase {
         const TileCfg t = TileSet<L>::get(i);
         if (t.T1 > G.N1 || t.T2 > G.N2) continue;
         if (wide_fits && t.NT < 64) continue;
-        // 3D: 4 x 64 tiles where they fit (fewer partial-line halo columns than
-        // 8 x 32 or 16 x 16; measured best at N = 128 and 256), else 8 x 32
-        if (D == 3 && G.N2 >= 64 && G.N1 >= 4 && !(t.T1 == 4 && t.T2 == 64)) continue;
-        if (D == 3 && t.T1 == 16 && G.N2 >= 32 && G.N1 >= 8) continue;
-        if (D == 3 && t.T1 < 4) continue;
+        // 3D: at N_z = 128 the 2 x 128 tile, which spans z and so has no z halo
+        // (measured at N = 128: 5% per step over 4 x 64); otherwise 4 x 64 tiles
+        // where they fit (fewer partial-line halo columns than 8 x 32 or 16 x 16;
+        // measured best at N = 256, where the 1 x 256 tile's two halo rows per
+        // row cost more), else 8 x 32
+        if (D == 3) {
+          if (G.N2 == 128 && G.N1 >= 2) {
+            if (!(t.T1 == 2 && t.T2 == 128)) continue;
+          } else if (G.N2 >= 64 && G.N1 >= 4) {
+            if (!(t.T1 == 4 && t.T2 == 64)) continue;
+          } else {
+            if (t.T1 == 16 && G.N2 >= 32 && G.N1 >= 8) continue;
+            if (t.T1 < 4) continue;
+          }
+        }
         // the largest tile that fits (measured best at every size; the strip
         // length below supplies the parallelism)
         best = i;
