@@ -466,8 +466,18 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
   }
 }
 
+// Minimum waves per SIMD of a sweep instantiation: the D2Q9 FP64 first sweep
+// of a step (three history states in flight) needs 266 registers and would
+// run one wave per SIMD; bounded to two it spills 40 bytes per lane and is
+// 9-12% faster per step at N = 512 and 1024 (3% slower at N = 256, where one
+// block per CU runs anyway).
+template <class L, class T, int MODE>
+__host__ __device__ constexpr int sweep_min_waves() {
+  return (L::D == 2 && sizeof(T) == 8 && MODE == SW_DTS_SETUP) ? 2 : 1;
+}
+
 template <class L, class T, class TM, int NT, int T1, int T2, int MODE>
-__global__ __launch_bounds__(NT) void k_sweep(SweepArgs<T, TM> A) {
+__global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(SweepArgs<T, TM> A) {
   using CT = typename CompT<T>::type;
   constexpr int Q = L::Q, D = L::D;
   constexpr int NI = T1 * T2;
