@@ -1948,20 +1948,23 @@ class Solver : public SolverBase {
 
   // FFT launch shapes
   // rows per block of the row passes: LDS-limited, and small enough that the
-  // grid has >= 128 blocks when the grid is large enough
+  // grid has >= 256 blocks (one per CU) when the grid is large enough (N = 512
+  // FP32: two rows per block instead of four cut the corrected march by 12%)
   int fft_rows_per_block(size_t c = sizeof(cpx<CT>)) const {
     int R = (int)std::max<size_t>(1, (size_t)65536 / (4 * G.N2 * c));
     int p = 1;
     while (p * 2 <= R) p *= 2;
-    while (p > 1 && G.N0 / p < 128) p >>= 1;
+    while (p > 1 && G.N0 / p < 256) p >>= 1;
     return std::min(p, G.N0);
   }
-  // columns per block of the column pass: LDS-limited, >= 64 blocks if possible
+  // columns per block of the column pass: LDS-limited, and as few as give
+  // >= 256 blocks (one per CU: at N = 512 one column per block instead of
+  // two cuts the corrected march by 7%, at N = 1024 FP32 by 5%)
   int fft_cols_per_block(size_t c = sizeof(cpx<CT>)) const {
     int J = (int)std::max<size_t>(1, (size_t)98304 / (6 * G.N0 * c));
     J = std::min(J, 16);
     const int NB = G.N2 / 4 + 1;
-    while (J > 1 && (NB + J - 1) / J < 64) J >>= 1;
+    while (J > 1 && (NB + J - 1) / J < 256) J >>= 1;
     return std::max(J, 1);
   }
 
