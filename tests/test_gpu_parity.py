@@ -124,6 +124,47 @@ def test_corrected_iteration_fp64(M, orc, shape):
     s.close()
 
 
+WIDE_SHAPES = [(512, 512), (1024, 128), (128, 1024)]
+
+
+@pytest.mark.parametrize("shape", WIDE_SHAPES)
+def test_corrected_iteration_wide_fp64(M, orc, shape):
+    """Rows longer than the widest sweep tile: the row transforms run as passes
+    of their own, and the column pass takes one j_y column per block (the
+    grids have >= 256 blocks where the extents allow)."""
+    say("correct wide", shape)
+    f, h = _rand_state(orc, 2, shape, seed=5 + sum(shape))
+    a = 3.0 / 128.0
+    s = _solver(M, shape)
+    fn, dm, R = s.correct(f, h, a)
+    ofn, _, _, odm, oR = orc.corrected_iteration(f, h, a, 1.0, 1.0, NU)
+    say("  rel dm", rel(dm, odm), "rel fn", rel(fn, ofn))
+    assert rel(dm, odm) <= 1e-12
+    assert rel(fn, ofn) <= 1e-12
+    assert abs(R - oR) <= 1e-12 * oR
+    s.close()
+
+
+def test_corrected_iteration_512_fp32(M, orc):
+    """FP32 storage at N = 512 (FP32 transforms, FP64 solve): the oracle takes
+    the FP32-rounded populations; the update is bounded by FP32 rounding of
+    the sweep output and of the transforms, <= 2e-6 max|f|, and the correction
+    field by <= 1e-5 of its own size."""
+    shape = (512, 512)
+    f, h = _rand_state(orc, 2, shape, seed=11)
+    a = 3.0 / 128.0
+    f32 = f.astype(np.float32).astype(np.float64)  # the stored input
+    s = _solver(M, shape, storage="fp32")
+    fn, dm, R = s.correct(f, h, a)
+    ofn, _, _, odm, oR = orc.corrected_iteration(f32, h, a, 1.0, 1.0, NU)
+    err = float(np.max(np.abs(fn - ofn)))
+    say("correct fp32 512: max err", err, "max|f|", float(np.max(np.abs(ofn))), "rel dm", rel(dm, odm), "R", R, oR)
+    assert err <= 2e-6 * float(np.max(np.abs(ofn)))
+    assert rel(dm, odm) <= 1e-5
+    assert abs(R - oR) <= 1e-3 * oR
+    s.close()
+
+
 def test_explicit_march_fp64(M, orc):
     say("explicit N=64")
     N = 64
