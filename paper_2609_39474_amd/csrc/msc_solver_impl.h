@@ -1948,13 +1948,14 @@ class Solver : public SolverBase {
 
   // FFT launch shapes
   // rows per block of the row passes: LDS-limited, and small enough that the
-  // grid has >= 256 blocks (one per CU) when the grid is large enough (N = 512
-  // FP32: two rows per block instead of four cut the corrected march by 12%)
+  // grid has >= 1024 blocks (four per CU) when the grid is large enough: these
+  // passes are latency-bound, and one row per block instead of four cuts the
+  // corrected march by 18% at N = 512 FP32, one instead of two by 4% at N = 1024
   int fft_rows_per_block(size_t c = sizeof(cpx<CT>)) const {
     int R = (int)std::max<size_t>(1, (size_t)65536 / (4 * G.N2 * c));
     int p = 1;
     while (p * 2 <= R) p *= 2;
-    while (p > 1 && G.N0 / p < 256) p >>= 1;
+    while (p > 1 && G.N0 / p < 1024) p >>= 1;
     return std::min(p, G.N0);
   }
   // columns per block of the column pass: LDS-limited, and as few as give
