@@ -29,6 +29,12 @@
 //   full-symbol reference ..... Sec. 4.1, Eq. (full-symbol): collision
 //                               Jacobian at rest, per-wavevector Q x Q solve
 //
+// Pins: the tests check this code against what the paper and mathematics fix
+// (identities, closed forms, printed tables, brute force on tiny grids).  The
+// trial extrapolation is pinned by its closed form (exact for population
+// histories polynomial in time); its effect on inner counts only loosely (the
+// printed 2.0-3.2 range): exact counts on random fields are parity unpinned.
+//
 // Readings where the paper is silent are listed in the design notes; the ones
 // that matter here: m^0 = P f^0; the extrapolation counts f^0 as an accepted
 // state; the mask is the integer test 4|j| <= N on signed indices; k in H is

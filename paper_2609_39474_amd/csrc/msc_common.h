@@ -210,18 +210,28 @@ __device__ inline void dev_rebuild(const _Float16* g, const float* M, float sig,
   }
 }
 
-// (g, M) from f.
-template <class L>
+// (g, M) from f.  The moments are summed in AT and rounded to FP32 once: in
+// the dual-time sweeps AT = double, because the inner fixed point amplifies a
+// systematic rounding of the conserved moments by about dt (as for the
+// collision's arithmetic); the explicit map sums in FP32.
+template <class L, class AT = float>
 __device__ inline void dev_split(const float* f, float isig, _Float16* g, float* M) {
+  AT acc[L::D + 1];
 #pragma unroll
-  for (int b = 0; b <= L::D; ++b) M[b] = 0.f;
+  for (int b = 0; b <= L::D; ++b) acc[b] = 0;
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) {
-    M[0] += f[k];
+    acc[0] += (AT)f[k];
 #pragma unroll
-    for (int b = 0; b < L::D; ++b)
-      if (ca<L>(k, b) != 0) M[1 + b] += (float)ca<L>(k, b) * f[k];
+    for (int b = 0; b < L::D; ++b) {
+      if (ca<L>(k, b) > 0)
+        acc[1 + b] += (AT)f[k];
+      else if (ca<L>(k, b) < 0)
+        acc[1 + b] -= (AT)f[k];
+    }
   }
+#pragma unroll
+  for (int b = 0; b <= L::D; ++b) M[b] = (float)acc[b];
 #pragma unroll
   for (int k = 0; k < L::Q; ++k) g[k] = (_Float16)((f[k] - feq_f32<L>(k, M)) * isig);
 }

@@ -64,7 +64,7 @@ __device__ inline void site_store(T* f, int64_t NS, int64_t s, float isig, const
   if constexpr (PopDev<T>::value) {
     _Float16 g[L::Q];
     float M[L::D + 1];
-    dev_split<L>(v, isig, g, M);
+    dev_split<L, double>(v, isig, g, M);
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) f[(int64_t)k * NS + s] = g[k];
     float* Ms = dev_moments(f, L::Q, NS);

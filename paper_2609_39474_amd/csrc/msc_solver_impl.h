@@ -13,6 +13,7 @@
 #include <hip/hip_ext.h>
 
 #include "msc_adjoint.h"
+#include "msc_sweep_launch.h"
 #include "msc_fullsym.h"
 #include "msc_walls.h"
 #include "msc_solver.h"
@@ -31,88 +32,6 @@ inline int ilog2(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
   return l;
-}
-
-// ----------------------------------------------------------- sweep dispatch --
-// Available tiles (T1 x T2 sites of the (p1, p2) plane, NT threads).
-struct TileCfg {
-  int T1, T2, NT;
-};
-
-template <class L>
-struct TileSet;
-template <>
-struct TileSet<D2Q9> {
-  static constexpr int count = 7;
-  static TileCfg get(int i) {
-    const TileCfg t[7] = {{1, 4, 4},     {1, 8, 8},     {1, 16, 16},  {1, 32, 32},
-                          {1, 64, 64},   {1, 128, 128}, {1, 256, 256}};
-    return t[i];
-  }
-};
-template <>
-struct TileSet<D3Q19> {
-  static constexpr int count = 7;
-  static TileCfg get(int i) {
-    const TileCfg t[7] = {{4, 4, 16}, {8, 8, 64}, {16, 16, 256}, {8, 32, 256}, {4, 64, 256}, {2, 128, 256},
-                          {1, 256, 256}};
-    return t[i];
-  }
-};
-
-// With ev0/ev1 the launch carries its own start/stop timestamps (kernel
-// timing), which adds no packets between this launch and its neighbours.
-template <class L, class T, class TM, int NT, int T1, int T2, int MODE>
-void launch_sweep_mode(const SweepArgs<T, TM>& A, int grid, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  if (ev0)
-    hipExtLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, MODE>), dim3(grid), dim3(NT), 0, st, ev0, ev1, 0, A);
-  else
-    hipLaunchKernelGGL((k_sweep<L, T, TM, NT, T1, T2, MODE>), dim3(grid), dim3(NT), 0, st, A);
-}
-
-template <class L, class T, class TM, int NT, int T1, int T2>
-void launch_sweep_tile(int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st, hipEvent_t ev0,
-                       hipEvent_t ev1) {
-  if (mode == SW_EXPLICIT)
-    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_EXPLICIT>(A, grid, st, ev0, ev1);
-  else if (mode == SW_DTS)
-    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS>(A, grid, st, ev0, ev1);
-  else if (mode == SW_DTS_LIFT)
-    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_LIFT>(A, grid, st, ev0, ev1);
-  else if (mode == SW_DTS_SETUP)
-    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_SETUP>(A, grid, st, ev0, ev1);
-  else if constexpr (T1 == 1 && NT == T2 && L::D == 2)
-    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_LIFT_ROWS>(A, grid, st, ev0, ev1);
-  else
-    throw DeviceError{hipErrorInvalidValue, "inverse-row lift requested for a tile that does not span rows"};
-}
-
-
-template <class T, class TM>
-void launch_sweep_d2(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-  switch (tile) {
-    case 0: launch_sweep_tile<D2Q9, T, TM, 4, 1, 4>(mode, A, grid, st, ev0, ev1); break;
-    case 1: launch_sweep_tile<D2Q9, T, TM, 8, 1, 8>(mode, A, grid, st, ev0, ev1); break;
-    case 2: launch_sweep_tile<D2Q9, T, TM, 16, 1, 16>(mode, A, grid, st, ev0, ev1); break;
-    case 3: launch_sweep_tile<D2Q9, T, TM, 32, 1, 32>(mode, A, grid, st, ev0, ev1); break;
-    case 4: launch_sweep_tile<D2Q9, T, TM, 64, 1, 64>(mode, A, grid, st, ev0, ev1); break;
-    case 5: launch_sweep_tile<D2Q9, T, TM, 128, 1, 128>(mode, A, grid, st, ev0, ev1); break;
-    default: launch_sweep_tile<D2Q9, T, TM, 256, 1, 256>(mode, A, grid, st, ev0, ev1); break;
-  }
-}
-template <class T, class TM>
-void launch_sweep_d3(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-  switch (tile) {
-    case 0: launch_sweep_tile<D3Q19, T, TM, 16, 4, 4>(mode, A, grid, st, ev0, ev1); break;
-    case 1: launch_sweep_tile<D3Q19, T, TM, 64, 8, 8>(mode, A, grid, st, ev0, ev1); break;
-    case 2: launch_sweep_tile<D3Q19, T, TM, 256, 16, 16>(mode, A, grid, st, ev0, ev1); break;
-    case 3: launch_sweep_tile<D3Q19, T, TM, 256, 8, 32>(mode, A, grid, st, ev0, ev1); break;
-    case 4: launch_sweep_tile<D3Q19, T, TM, 256, 4, 64>(mode, A, grid, st, ev0, ev1); break;
-    case 5: launch_sweep_tile<D3Q19, T, TM, 256, 2, 128>(mode, A, grid, st, ev0, ev1); break;
-    default: launch_sweep_tile<D3Q19, T, TM, 256, 1, 256>(mode, A, grid, st, ev0, ev1); break;
-  }
 }
 
 // Buffers of one run of the correction transforms in one precision.
@@ -1043,9 +962,12 @@ class Solver : public SolverBase {
   // explicit-march graph cache
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  // key of the captured explicit-march graph: the sweep arguments it holds by
+  // value (buffers, chunk length and the deviation-storage scale)
   const T* g_a = nullptr;
   const T* g_b = nullptr;
   int g_chunk = 0;
+  float g_sig = 0.0f;
 
   // kernel timing
   bool timing = false;
@@ -1653,54 +1575,10 @@ class Solver : public SolverBase {
         if (t.T1 * t.T2 == tune.sweep_tile && t.T1 <= G.N1 && t.T2 <= G.N2) best = i;
       }
     }
-    if (best < 0) {
-      bool wide_fits = false;  // some tile with a full wavefront fits
-      for (int i = 0; i < n; ++i) {
-        const TileCfg t = TileSet<L>::get(i);
-        if (t.T1 <= G.N1 && t.T2 <= G.N2 && t.NT >= 64) wide_fits = true;
-      }
-      for (int i = 0; i < n; ++i) {
-        const TileCfg t = TileSet<L>::get(i);
-        if (t.T1 > G.N1 || t.T2 > G.N2) continue;
-        if (wide_fits && t.NT < 64) continue;
-        // 3D: at N_z = 128 the 2 x 128 tile, which spans z and so has no z halo
-        // (measured at N = 128: 5% per step over 4 x 64); otherwise 4 x 64 tiles
-        // where they fit (fewer partial-line halo columns than 8 x 32 or 16 x 16;
-        // measured best at N = 256, where the 1 x 256 tile's two halo rows per
-        // row cost more), else 8 x 32
-        if (D == 3) {
-          if (G.N2 == 128 && G.N1 >= 2) {
-            if (!(t.T1 == 2 && t.T2 == 128)) continue;
-          } else if (G.N2 >= 64 && G.N1 >= 4) {
-            if (!(t.T1 == 4 && t.T2 == 64)) continue;
-          } else {
-            if (t.T1 == 16 && G.N2 >= 32 && G.N1 >= 8) continue;
-            if (t.T1 < 4) continue;
-          }
-        }
-        // the largest tile that fits (measured best at every size; the strip
-        // length below supplies the parallelism)
-        best = i;
-      }
-    }
+    if (best < 0) best = auto_sweep_tile<L>(G.N1, G.N2);
     tile_id = best;
     tile = TileSet<L>::get(best);
-    const int64_t tiles = (int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2);
-    int Lp = tune.sweep_strip;
-    if (Lp <= 0) {
-      // Longest strip (at most 64 planes in 2D, 32 in 3D) that keeps >= 1024
-      // blocks (2D) or >= 512 (3D, more work per site): short strips cut the
-      // per-block chain of plane steps, which bounds small grids; long ones
-      // cut the two halo planes per strip.  Measured optimum of the sweep at
-      // N = 256 ... 4096 (2D) and N = 64 ... 256 (3D).
-      const int64_t target = (D == 2) ? 1024 : 512;
-      const int Lmax = (D == 2) ? 64 : 32;
-      Lp = 1;
-      while (Lp < Lmax && tiles * (G.N0 / (Lp * 2)) >= target) Lp *= 2;
-    }
-    Lp = std::min(Lp, G.N0);
-    while (G.N0 % Lp) Lp >>= 1;
-    strip_L = std::max(Lp, 1);
+    strip_L = sweep_strip_for<L>(tile, G.N0, G.N1, G.N2, tune.sweep_strip);
     fuse_rows = D == 2 && P.corrector == MSC_CORRECTOR_SHADOW && tile.T1 == 1 && tile.T2 == G.N2 &&
                 tile.NT == tile.T2 && corrector_supported() && tune.fuse_rows != 0;
     fuse_inv = fuse_rows && strip_L == 1 && tune.fuse_rows >= 2;
@@ -1819,7 +1697,7 @@ class Solver : public SolverBase {
   }
 
   hipGraphExec_t explicit_graph(T* A, T* B, int chunk) {
-    if (gexec && g_a == A && g_b == B && g_chunk == chunk) return gexec;
+    if (gexec && g_a == A && g_b == B && g_chunk == chunk && g_sig == sig) return gexec;
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     gexec = nullptr;
@@ -1840,6 +1718,7 @@ class Solver : public SolverBase {
     g_a = A;
     g_b = B;
     g_chunk = chunk;
+    g_sig = sig;
     return gexec;
   }
 

@@ -391,30 +391,38 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
       f[k] += (CT)L::w(k) * (d0 + (CT)3 * cu);
     }
   }
-  CT M[4] = {0, 0, 0, 0};
+  // Collision arithmetic type: FP64 temporaries in the dual-time modes of
+  // every storage type.  The inner fixed point amplifies the rounding of the
+  // collision's conserved moments by about dt (the slow hydrodynamic modes of
+  // I - J have eigenvalues near a_q), so FP32 arithmetic there would put an
+  // error of ~eps32 dt sqrt(S) on the velocity; the populations, the trial
+  // and the residual stay in the storage's compute type.  The explicit map
+  // has no such amplification and keeps the compute type.
+  using KT = typename std::conditional<MODE == SW_EXPLICIT, CT, double>::type;
+  KT M[4] = {0, 0, 0, 0};
   if constexpr (DV) {
     // deviation storage keeps P f itself: combine the stored FP32 moments
     // (P of the rebuild is exactly M; P of the lift E dm is dm)
 #pragma unroll
     for (int b = 0; b <= D; ++b) {
       if constexpr (MODE == SW_DTS_SETUP)
-        M[b] = (A.order == 0) ? r.M0[b]
-                              : (A.order == 1 ? (CT)2 * r.M0[b] - r.M1[b]
-                                              : (CT)3 * r.M0[b] - (CT)3 * r.M1[b] + r.M2[b]);
+        M[b] = (A.order == 0) ? (KT)r.M0[b]
+                              : (A.order == 1 ? (KT)2 * (KT)r.M0[b] - (KT)r.M1[b]
+                                              : (KT)3 * (KT)r.M0[b] - (KT)3 * (KT)r.M1[b] + (KT)r.M2[b]);
       else
-        M[b] = r.M0[b];
-      if constexpr (lift_mode(MODE)) M[b] += (CT)r.dmv[b];
+        M[b] = (KT)r.M0[b];
+      if constexpr (lift_mode(MODE)) M[b] += (KT)r.dmv[b];
     }
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      M[0] += f[k];
+      M[0] += (KT)f[k];
 #pragma unroll
       for (int b = 0; b < D; ++b)
-        if (ca<L>(k, b) != 0) M[1 + b] += (CT)ca<L>(k, b) * f[k];
+        if (ca<L>(k, b) != 0) M[1 + b] += (KT)ca<L>(k, b) * (KT)f[k];
     }
   }
-  CT m[4], s[4];
+  KT m[4], s[4];
   if (MODE == SW_EXPLICIT) {
 #pragma unroll
     for (int b = 0; b <= D; ++b) {
@@ -427,42 +435,62 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
 #pragma unroll
     for (int b = 0; b <= D; ++b) {
       const double mb = ((double)M[b] + 0.5 * h[b]) * A.inv1pa2;
-      m[b] = (CT)mb;
-      s[b] = (CT)(h[b] - A.a * mb);
+      m[b] = (KT)mb;
+      s[b] = (KT)(h[b] - A.a * mb);
     }
   }
-  const CT uu = m[1] * m[1] + m[2] * m[2] + (D == 3 ? m[3] * m[3] : (CT)0);
-  CT feq[Q], phi[Q];
+  // Equilibrium (Eq. feq) and source distribution (Eq. source-distribution)
+  // split into the parts even and odd under k -> opposite(k), which is what
+  // the TRT update (Eq. collision) takes: with cu = c_k.u and cs = c_k.s_u,
+  //   feq+ = w (p - 1.5 u.u + 4.5 cu^2),   feq- = 3 w cu,
+  //   Phi+ = w (s_0 - 3 u.s_u + 9 cu cs),  Phi- = 3 w cs,
+  // so each pair of opposite directions is collided from two dot products.
+  KT uu = 0, us = 0;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    CT cu = 0;
-#pragma unroll
-    for (int b = 0; b < D; ++b)
-      if (ca<L>(k, b) != 0) cu += (CT)ca<L>(k, b) * m[1 + b];
-    const CT wk = (CT)L::w(k);
-    feq[k] = wk * (m[0] + (CT)3 * cu + (CT)4.5 * cu * cu - (CT)1.5 * uu);
-    if (MODE == SW_EXPLICIT) {
-      phi[k] = 0;
-    } else {
-      CT ps = s[0];
-#pragma unroll
-      for (int b = 0; b < D; ++b)
-        ps += ((CT)3 * ((CT)ca<L>(k, b) - m[1 + b]) + (CT)9 * cu * (CT)ca<L>(k, b)) * s[1 + b];
-      phi[k] = wk * ps;
-    }
+  for (int b = 1; b <= D; ++b) {
+    uu += m[b] * m[b];
+    us += m[b] * s[b];
   }
-  const CT wp = (CT)A.wp, wm = (CT)A.wm;
-  const CT hp = (CT)1 - (CT)0.5 * wp, hm = (CT)1 - (CT)0.5 * wm;
+  const KT Be = m[0] - (KT)1.5 * uu;
+  const KT Ae = s[0] - (KT)3 * us;
+  const KT wp = (KT)A.wp, wm = (KT)A.wm;
+  const KT hp = (KT)1 - (KT)0.5 * wp, hm = (KT)1 - (KT)0.5 * wm;
+  const KT gp = (KT)1 - wp, gm = (KT)1 - wm;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     const int kb = L::opp(k);
-    const CT fp = (CT)0.5 * (f[k] + f[kb]), fm = (CT)0.5 * (f[k] - f[kb]);
-    const CT ep = (CT)0.5 * (feq[k] + feq[kb]), em = (CT)0.5 * (feq[k] - feq[kb]);
-    C[k] = f[k] - wp * (fp - ep) - wm * (fm - em);
-    if (MODE != SW_EXPLICIT) {
-      const CT pp = (CT)0.5 * (phi[k] + phi[kb]), pm = (CT)0.5 * (phi[k] - phi[kb]);
-      C[k] += hp * pp + hm * pm;
+    if (kb < k) continue;
+    const KT wk = (KT)L::w(k);
+    const KT fk = (KT)f[k];
+    if (kb == k) {
+      // rest direction: only even parts
+      KT ck = gp * fk + wp * (wk * Be);
+      if (MODE != SW_EXPLICIT) ck += hp * (wk * Ae);
+      C[k] = (CT)ck;
+      continue;
     }
+    KT cu = 0, cs = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      if (ca<L>(k, b) > 0) {
+        cu += m[1 + b];
+        if (MODE != SW_EXPLICIT) cs += s[1 + b];
+      } else if (ca<L>(k, b) < 0) {
+        cu -= m[1 + b];
+        if (MODE != SW_EXPLICIT) cs -= s[1 + b];
+      }
+    }
+    const KT fkb = (KT)f[kb];
+    const KT fp = (KT)0.5 * (fk + fkb), fm = (KT)0.5 * (fk - fkb);
+    const KT ep = wk * (Be + (KT)4.5 * cu * cu), em = (KT)3 * wk * cu;
+    KT ev = gp * fp + wp * ep;
+    KT od = gm * fm + wm * em;
+    if (MODE != SW_EXPLICIT) {
+      ev += hp * (wk * (Ae + (KT)9 * cu * cs));
+      od += hm * ((KT)3 * wk * cs);
+    }
+    C[k] = (CT)(ev + od);
+    C[kb] = (CT)(ev - od);
   }
 }
 
@@ -471,9 +499,13 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
 // run one wave per SIMD; bounded to two it spills 40 bytes per lane and is
 // 9-12% faster per step at N = 512 and 1024 (3% slower at N = 256, where one
 // block per CU runs anyway).
+// The D2Q9 FP32 dual-time and lift sweeps need 129-131 registers, one or
+// three above the 128 that allow four waves per SIMD; bounded to four.
 template <class L, class T, int MODE>
 __host__ __device__ constexpr int sweep_min_waves() {
-  return (L::D == 2 && sizeof(T) == 8 && MODE == SW_DTS_SETUP) ? 2 : 1;
+  return (L::D == 2 && sizeof(T) == 8 && MODE == SW_DTS_SETUP)                          ? 2
+         : (L::D == 2 && sizeof(T) == 4 && (MODE == SW_DTS || MODE == SW_DTS_LIFT)) ? 4
+                                                                                       : 1;
 }
 
 template <class L, class T, class TM, int NT, int T1, int T2, int MODE>
@@ -723,7 +755,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
           // measures (and its fixed point has r = 0)
           T gq[Q];
           float Mq[D + 1];
-          dev_split<L>(vv, A.isig, gq, Mq);
+          dev_split<L, typename std::conditional<MODE == SW_EXPLICIT, float, double>::type>(vv, A.isig, gq, Mq);
 #pragma unroll
           for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(gq[k], &dst[k * NS + site]);
           float* dM = dev_moments(dst, Q, NS);

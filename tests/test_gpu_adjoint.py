@@ -15,9 +15,14 @@ import pytest
 
 from paper_2609_39474_amd import workloads as W
 
+import parity_bars as PB
+
 pytestmark = pytest.mark.gpu
 
 NU = 1.0 / 6.0
+# FP32-storage loss gradient against the FP64 one at N = 256 (max norm):
+# twice the value measured on MI355X
+BAR_FP32_GRAD = 2 * 6.9e-4
 
 
 def say(*a):
@@ -109,6 +114,52 @@ def test_adjoint_vs_oracle_fp64(M, orc, shape, dt, corr, extrap, nsteps):
     say("  K", K, "rel", e)
     assert e <= 1e-10
     s.close()
+
+
+def test_adjoint_vs_oracle_n256_fp64(M, orc):
+    """The differentiable march at its own size (N = 256, 20 steps of dt = 64,
+    eps = 1e-8, FP64 storage): the GPU adjoint of the recorded march against
+    the oracle's discrete adjoint from the same start state at the same inner
+    counts, for the output adjoint of the misfit to the 20-step endpoint of
+    the seed-2 field.  Bar per part: 1e-10, or ten times the oracle's own
+    sensitivity to a one-ulp change of the start state where that is larger
+    (with the paper's trial rule the population adjoint is ill-conditioned:
+    the oracle itself moves by ~3e-6 relative; the moment parts do not)."""
+    cfg = W.config("vort2d_n256_adjoint")
+    N, nsteps, dt, U = cfg["N"], cfg["nsteps"], cfg["dt"], cfg["U"]
+    shape = (N, N)
+    Q, NS = 9, N * N
+    p0, u0 = W.random_field_2d(N, U, seed=cfg["seed"])
+    pB, uB = W.random_field_2d(N, U, seed=cfg["target_seed"])
+    t = _solver(M, shape, pB, uB, dt=dt, eps=cfg["eps"])
+    rc, _ = t.bdf2_step(nsteps)
+    assert rc == 0
+    ustar = t.moments()[1:]
+    t.close()
+    s = _solver(M, shape, p0, u0, dt=dt, eps=cfg["eps"])
+    st0, bc0 = s.get_state()
+    s.set_recording(True)
+    rc, stats = s.bdf2_step(nsteps)
+    assert rc == 0 and s.recorded_steps() == nsteps
+    K = [x["iters"] for x in stats]
+    st1, _ = s.get_state()
+    L, lam = _loss_grad(st1, shape, ustar, Q)
+    say("n256 adjoint vs oracle: K", K, "loss", L)
+    g = s.bdf2_adjoint(nsteps, lam)
+    s.close()
+    kw = dict(dt=dt, eps=cfg["eps"], corrector=1, extrap_states=0, nmin=2, kmax=300)
+    ref = orc.march_adjoint(st0, bc0, shape, lam, schedule=K, **kw)
+    alt = orc.march_adjoint(PB.ulp_perturbed(st0, 1), bc0, shape, lam, schedule=K, **kw)
+    FQ = Q * NS
+
+    def parts(x):
+        return [x[:3 * FQ]] + [x[3 * FQ + i * NS:3 * FQ + (i + 1) * NS] for i in range(6)]
+
+    keep = [i for i, b in enumerate(parts(ref)) if np.max(np.abs(b)) > 0]
+    errs = [rel(parts(g)[i], parts(ref)[i]) for i in keep]
+    sens = [rel(parts(alt)[i], parts(ref)[i]) for i in keep]
+    say("  rel per part (populations, m^n fields)", errs, "oracle one-ulp sensitivity", sens)
+    PB.check_fields(errs, PB.sensitivity_bars(sens, floor=1e-10), "adjoint n256")
 
 
 def test_adjoint_split_calls_and_errors(M):
@@ -286,9 +337,9 @@ def test_adjoint_vorticity_control_n256(M):
     vorticity, loss against the 20-step endpoint of the seed-2 vorticity.
     FP64: eight directional central differences (h = 1e-3 relative, replayed
     inner counts) within 1e-4.  FP32 storage (same counts): gradient error
-    relative to FP64 measured and bounded (5e-3 in the max norm; it is the
-    FP32 forward's error carried by the loss gradient, see the FP32 test
-    above)."""
+    relative to FP64 measured and bounded (the FP32 forward's error carried
+    by the loss gradient; the precision policy's stated result, with a fixed
+    bar of twice the measured max-norm error)."""
     import torch
 
     from paper_2609_39474_amd import autograd as AG
@@ -335,4 +386,4 @@ def test_adjoint_vorticity_control_n256(M):
     e32_l2 = float((grads["fp32"] - g).norm() / g.norm())
     say("  worst FD rel", worst, "; FP32 gradient rel error: max-norm", e32, "L2", e32_l2)
     assert worst <= 1e-4
-    assert e32 <= 5e-3
+    assert e32 <= BAR_FP32_GRAD

@@ -39,6 +39,11 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
 
 
+def rel_fields(a, b):
+    """rel() of each moment field (p-hat, u_x, u_y[, u_z]) at its own scale."""
+    return max(rel(np.asarray(a)[i], np.asarray(b)[i]) for i in range(np.asarray(b).shape[0]))
+
+
 def _solver(M, shape, *, ulid, dt=16.0, eps=1e-10, corrector="wall_kinetic", storage="fp64", n_min=1,
             k_max=600, wall_operator="frozen", wall_forced=0, tau=(1.0, 1.0)):
     p = M.make_params(2, shape[0], dt=dt, eps=eps, storage=storage, corrector=corrector, n_min=n_min, k_max=k_max,
@@ -104,8 +109,8 @@ def test_cavity_picard_march(M, orc):
     s.set_schedule(K)
     rc, stats = s.bdf2_step(3)
     assert rc == 0 and [x["iters"] for x in stats] == K
-    say("cavity Picard march", K, rel(s.moments(), ref["m"]))
-    assert rel(s.moments(), ref["m"]) <= 1e-11
+    say("cavity Picard march", K, rel_fields(s.moments(), ref["m"]))
+    assert rel_fields(s.moments(), ref["m"]) <= 1e-11
     s.close()
 
 
@@ -151,14 +156,14 @@ def test_wall_kinetic_march(M, orc, operator, forced):
     rc, stats = s.bdf2_step(4)
     assert rc == 0 and [x["iters"] for x in stats] == K
     assert [x["refreshes"] for x in stats] == refr
-    e = rel(s.moments(), ref["m"])
+    e = rel_fields(s.moments(), ref["m"])
     say("wall-kinetic march", operator, "counts", K, "refreshes", refr, "rel", e, "krylov", s.krylov_stats())
     assert e <= 1e-8
     s.close()
     s = _solver(M, (N, N), ulid=ulid, dt=dt, wall_operator=operator, wall_forced=forced)
     rc, stats = s.bdf2_step(4)
     assert rc == 0 and [x["iters"] for x in stats] == K
-    assert rel(s.moments(), ref["m"]) <= 1e-8
+    assert rel_fields(s.moments(), ref["m"]) <= 1e-8
     s.close()
 
 

@@ -4,21 +4,26 @@ transform shapes, the dual-time march through msc_bdf2_step): the FP64
 oracle marches the same seeded inputs with the same parameters and its inner
 counts are replayed on the GPU.
 
-* D2Q9 N = 256, FP32 storage, dt = 256, eps = 1e-8, linear trial (the
-  benchmark's headline configuration);
-* D2Q9 N = 1024, FP32 and FP16-deviation storage, dt = 9830.4, eps = 1e-8;
-* D3Q19 N = 128, FP32 storage, dt = 63.83, eps = 1e-8, n_min = 2.
+* D3Q19 N = 128, FP64 storage, dt = 63.83, eps = 1e-10, n_min = 2 (the
+  benchmark's headline configuration): every field <= 1e-12 relative;
+* D3Q19 N = 128, FP32 storage, the same run;
+* D2Q9 N = 256, FP32 storage, dt = 256 and dt = 64, eps = 1e-8, linear trial;
+* D2Q9 N = 1024, FP32 and FP16-deviation storage, eps = 1e-8: Re = 1 and
+  Re = 1e-4 at dt = 9830.4 (S = 64 of the horizon 0.1 N^2/nu), Re = 100 at
+  dt = 2457.6 (S = 256: the largest step of the candidate set at which the
+  oracle converges; at dt = 9830.4 it diverges and at 4915.2 it reaches
+  K_max, as the paper's stability scan leads one to expect).
 
-Bar: RMS velocity error relative to the FP64 oracle, and the replayed counts
-are reached.  For FP32 (and FP16-deviation, whose moments are FP32) storage
-the error is set by FP32 rounding of the populations and of the sweep's
-arithmetic, amplified by the dual-time system: a rounding perturbation of a
+Bars for FP32 and FP16-deviation storage: RMS error of each velocity
+component relative to that component's RMS in the FP64 oracle.  The error is
+FP32 rounding amplified by the dual-time system: a rounding perturbation of a
 sweep output moves the inner fixed point by about dt times as much (the slow
-hydrodynamic modes of I - T have eigenvalues near a = 3/(2 dt)), and the S
-steps add it up like a random walk.  Measured: 0.5 eps32 dt sqrt(S) (eps32 =
-2^-24) at dt = 64 and 256, N = 128 and 256; so the bar here is
-max(1e-5, 2 eps32 dt sqrt(S)): 1e-5 (the FP32 bar of the other parity tests)
-up to dt ~ 100, growing linearly beyond.
+hydrodynamic modes of I - T have eigenvalues near a = 3/(2 dt)).  The
+collision therefore runs with FP64 temporaries in the dual-time sweeps
+(populations stay FP32) and FP16-deviation storage sums its stored moments
+in FP64; with that every FP32 case here meets 1e-5 (measured 5e-7 to 2e-6,
+N = 1024 at dt = 9830.4 included).  A case that does not is listed in
+BAR_MISS with twice its measured error as the bar.
 """
 import math
 import sys
@@ -29,6 +34,10 @@ import pytest
 from paper_2609_39474_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+# FP16-deviation storage at N = 1024 (three steps), measured on MI355X: the
+# bar is twice the measured value where it does not meet 1e-5
+BAR_MISS = {}
 
 
 def say(*a):
@@ -43,42 +52,104 @@ def M():
     return msc
 
 
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
 def _vel_err(m, ref):
-    return math.sqrt(((m[1:] - ref[1:]) ** 2).sum(0).mean()) / math.sqrt((ref[1:] ** 2).sum(0).mean())
+    """Worst component of the RMS velocity error relative to that component's RMS."""
+    d = m.shape[0] - 1
+    return max(math.sqrt(((m[c] - ref[c]) ** 2).mean()) / math.sqrt((ref[c] ** 2).mean()) for c in range(1, d + 1))
 
 
-def _replay(M, orc, name, storage, nsteps, extrap):
-    cfg = W.config(name)
+_ORACLE = {}
+
+
+def _cfg(name, Re=None, dt=None, eps=None):
+    cfg = dict(W.config(name))
+    if Re is not None:
+        cfg["Re"] = Re
+        cfg["U"] = Re * cfg["nu"] / cfg["N"]
+    if dt is not None:
+        cfg["dt"] = dt
+    if eps is not None:
+        cfg["eps"] = eps
+    return cfg
+
+
+def _oracle(orc, cfg, nsteps, extrap):
+    key = (cfg["name"], cfg["Re"], cfg["dt"], cfg["eps"], nsteps, extrap)
+    if key not in _ORACLE:
+        p0, u0 = W.initial_fields(cfg)
+        say(f"oracle march of {nsteps} steps: {key}")
+        ref = orc.march(p0, u0, dt=cfg["dt"], nsteps=nsteps, eps=cfg["eps"], nmin=cfg["nmin"], extrap_states=extrap)
+        assert ref.status == 0
+        _ORACLE[key] = (p0, u0, ref)
+    return _ORACLE[key]
+
+
+def _replay(M, orc, cfg, storage, nsteps, extrap):
     d, N = cfg["d"], cfg["N"]
-    p0, u0 = W.initial_fields(cfg)
-    say(f"{name} {storage}: oracle march of {nsteps} steps at N = {N}")
-    ref = orc.march(p0, u0, dt=cfg["dt"], nsteps=nsteps, eps=cfg["eps"], nmin=cfg["nmin"], extrap_states=extrap)
-    assert ref.status == 0
+    p0, u0, ref = _oracle(orc, cfg, nsteps, extrap)
     K = [st["iters"] for st in ref.stats]
+    say(f"{cfg['name']} Re={cfg['Re']:g} dt={cfg['dt']:g} {storage}: counts {K}")
     p = M.make_params(d, N, dt=cfg["dt"], eps=cfg["eps"], storage=storage, corrector="shadow", n_min=cfg["nmin"],
                       extrap_states=extrap)
     s = M.Solver(p, p0, u0)
     s.set_schedule(K)
     rc, stats = s.bdf2_step(nsteps)
     assert rc == 0 and [x["iters"] for x in stats] == K
-    err = _vel_err(s.moments(), ref.m)
-    bar = max(1e-5, 2.0 * 2.0 ** -24 * cfg["dt"] * math.sqrt(nsteps))
-    say(f"  counts {K}, RMS velocity error relative to the oracle {err:.3e}, bar {bar:.3e}")
+    m = s.moments()
     s.close()
-    return err, bar
+    return m, ref
 
 
-def test_headline_config_n256_fp32(M, orc):
-    err, bar = _replay(M, orc, "rand2d_n256_fp32", "fp32", 8, 2)
+def test_headline_d3q19_n128_fp64(M, orc):
+    """The benchmark's headline run (D3Q19 N = 128, FP64): every field of the
+    hydrodynamic state after two steps, each at its own scale."""
+    cfg = _cfg("tgv3d_n128_fp32", eps=1e-10)
+    m, ref = _replay(M, orc, cfg, "fp64", 2, 2)
+    errs = [rel(m[i], ref.m[i]) for i in range(4)]
+    say("  per-field rel (p, ux, uy, uz)", errs)
+    assert max(errs) <= 1e-12
+
+
+def test_d3q19_n128_fp32(M, orc):
+    """Same run with FP32 storage (the oracle's counts at eps = 1e-10 are
+    replayed; the tolerance does not enter a replayed march)."""
+    cfg = _cfg("tgv3d_n128_fp32", eps=1e-10)
+    m, ref = _replay(M, orc, cfg, "fp32", 2, 2)
+    err = _vel_err(m, ref.m)
+    say(f"  velocity error {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("dt", [256.0, 64.0])
+def test_n256_fp32(M, orc, dt):
+    cfg = _cfg("rand2d_n256_fp32", dt=dt)
+    m, ref = _replay(M, orc, cfg, "fp32", 8, 2)
+    err = _vel_err(m, ref.m)
+    say(f"  velocity error {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16dev"])
+@pytest.mark.parametrize("Re", [1.0, 1e-4])
+def test_n1024_dt9830(M, orc, storage, Re):
+    cfg = _cfg("rand2d_n1024_fp32", Re=Re)
+    m, ref = _replay(M, orc, cfg, storage, 3, 2)
+    err = _vel_err(m, ref.m)
+    bar = BAR_MISS.get((storage, Re), 1e-5)
+    say(f"  velocity error {err:.3e} (bar {bar:.1e})")
     assert err <= bar
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16dev"])
-def test_n1024(M, orc, storage):
-    err, bar = _replay(M, orc, "rand2d_n1024_fp32", storage, 3, 2)
-    assert err <= bar
-
-
-def test_d3q19_n128_fp32(M, orc):
-    err, bar = _replay(M, orc, "tgv3d_n128_fp32", "fp32", 2, 2)
+def test_n1024_re100(M, orc, storage):
+    cfg = _cfg("rand2d_n1024_fp32", Re=100.0, dt=629146 / 256)
+    m, ref = _replay(M, orc, cfg, storage, 3, 2)
+    err = _vel_err(m, ref.m)
+    bar = BAR_MISS.get((storage, 100.0), 1e-5)
+    say(f"  velocity error {err:.3e} (bar {bar:.1e})")
     assert err <= bar
