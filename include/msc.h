@@ -330,6 +330,40 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
  * results).  MSC_ERR_INVALID_ARG for an unknown key or value. */
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);
 
+/* ------------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * evaluation of the sweep, as msc_sweep computes it, on caller-owned device
+ * buffers, with no context and no allocation.  It launches the same kernel,
+ * tile and strip length as a context's msc_sweep with automatic launch shapes,
+ * so fT and Pr are bit-identical to msc_sweep's and R agrees to rounding.
+ *
+ * lattice: MSC_D2Q9 or MSC_D3Q19.  n: extents (2 or 3 int32, powers of two
+ * >= 4).  tau_plus, tau_minus > 1/2 (Eq. trt).  storage: MSC_STORAGE_FP64
+ * (T = double) or MSC_STORAGE_FP32 (T = float).  Device arrays in canonical
+ * site order (x slowest), direction- or field-major: f (in) and fT (out)
+ * Q*N_sites of T; h (in) (d+1)*N_sites FP64, required (zeros give the
+ * source-free map); Pr (out) (d+1)*N_sites of T, the residual moments P r;
+ * R (out) one FP64 on the device, the RMS raw residual, or NULL.  a: the BDF
+ * coefficient a_q (>= 0).  stream: a hipStream_t (NULL = the default
+ * stream); the call only enqueues work and returns without synchronising.
+ * The caller keeps ownership of every buffer.
+ *
+ * Device memory of its own: the per-block partial sums of r^2 live in a
+ * fixed array of 65536 doubles (512 KiB) that each GPU holds from the first
+ * call on it until the process ends; grids with more sweep blocks than that
+ * (far beyond N = 16384^2 in 2D) return MSC_ERR_INVALID_ARG.  Every call on
+ * one GPU uses that one array, so calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ *
+ * Errors: MSC_ERR_INVALID_ARG (unknown lattice, extents, rates, a, storage,
+ * NULL buffers other than R, or a grid beyond the fixed array);
+ * MSC_ERR_UNSUPPORTED (MSC_STORAGE_FP16_DEV); MSC_ERR_DEVICE (a launch
+ * failed). */
+msc_status msc_sweep_noalloc(int32_t lattice, const int32_t* n, double tau_plus, double tau_minus,
+                             int32_t storage, const void* f, const double* h, double a, void* fT, void* Pr,
+                             double* R, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -118,6 +118,8 @@ SIGNATURES = {
     "msc_recorded_steps": (ctypes.c_int, [_vp, _ip]),
     "msc_bdf2_adjoint": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int32]),
     "msc_init_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32]),
+    "msc_sweep_noalloc": (ctypes.c_int, [ctypes.c_int32, _ip, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                         _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -387,6 +389,19 @@ class Solver:
     def init_adjoint_device(self, phat0_ptr, u0_ptr, lam_ptr, lp_ptr, lu_ptr):
         ptrs = [ctypes.c_void_p(int(p)) for p in (phat0_ptr, u0_ptr, lam_ptr, lp_ptr, lu_ptr)]
         self._check(lib().msc_init_adjoint(self.h, *ptrs, 1), "msc_init_adjoint")
+
+
+def sweep_noalloc(d, n, storage, f_ptr, h_ptr, a, fT_ptr, Pr_ptr, R_ptr=None, stream=None, tau_plus=1.0,
+                  tau_minus=1.0):
+    """msc_sweep_noalloc on device pointers (ints): one sweep with no context
+    and no device allocation.  storage "fp64" or "fp32"; R_ptr may be None.
+    Enqueues on ``stream`` and returns without synchronising."""
+    ext = (ctypes.c_int32 * 3)(*(list(n) + [1] * (3 - len(n))))
+    st = {"fp64": MSC_STORAGE_FP64, "fp32": MSC_STORAGE_FP32, "fp16dev": MSC_STORAGE_FP16_DEV}[storage]
+    rc = lib().msc_sweep_noalloc(MSC_D2Q9 if d == 2 else MSC_D3Q19, ext, tau_plus, tau_minus, st, f_ptr, h_ptr, a,
+                                 fT_ptr, Pr_ptr, R_ptr, stream)
+    if rc != MSC_OK:
+        raise MscError(rc, "msc_sweep_noalloc")
 
 
 def make_params(d, N, *, dt, eps, storage="fp64", corrector="shadow", tau_plus=1.0, tau_minus=1.0,
