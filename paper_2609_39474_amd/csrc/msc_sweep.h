@@ -334,7 +334,7 @@ __device__ __forceinline__ void load_raw(const SweepArgs<T, TM>& A, const SrcPtr
 template <class L, class T, class TM, int MODE>
 __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const RawSite<L, T, TM, MODE>& r,
                                             typename CompT<T>::type* f, typename CompT<T>::type* C,
-                                            double* hout) {
+                                            double* hout, double* Mtrial = nullptr) {
   using CT = typename CompT<T>::type;
   constexpr int Q = L::Q, D = L::D;
   constexpr bool DV = PopDev<T>::value;
@@ -420,6 +420,12 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
 #pragma unroll
       for (int b = 0; b < D; ++b)
         if (ca<L>(k, b) != 0) M[1 + b] += (KT)ca<L>(k, b) * (KT)f[k];
+    }
+  }
+  if constexpr (DV) {
+    if (Mtrial) {
+#pragma unroll
+      for (int b = 0; b <= D; ++b) Mtrial[b] = (double)M[b];
     }
   }
   KT m[4], s[4];
@@ -571,6 +577,9 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
   const int tid = threadIdx.x;
 
   CT fprev[SPT][Q], fcur[SPT][Q];
+  // deviation storage: the trial's moments at the owned sites, for P r
+  constexpr int NMT = (PopDev<T>::value && MODE != SW_EXPLICIT) ? D + 1 : 1;
+  double mprev[SPT][NMT], mcur[SPT][NMT];
   CT c0prev[SPT], cpx1[SPT], cpx2[SPT], cmxc[SPT], c0c[SPT], cpxc[SPT];
   RawSite<L, T, TM, MODE> raw[SPT];
   double r2 = 0.0;
@@ -655,7 +664,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
       }
       CT C[Q];
       double hs[4];
-      collide_raw<L, T, TM, MODE>(A, cur, fcur[j], C, hs);
+      collide_raw<L, T, TM, MODE>(A, cur, fcur[j], C, hs, mcur[j]);
       if (MODE == SW_DTS_SETUP && it >= 1 && it <= A.L) {
         const int64_t site = ((int64_t)xs * N1 + (b1 + i1)) * N2 + (b2 + i2);
 #pragma unroll
@@ -749,12 +758,12 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
         if constexpr (L::D == 2) {
           if (A.walls) cavity_rows<CT>(vv, xd, b2 + i2, N0, N2, (CT)A.ulid);
         }
+        float Mq[PopDev<T>::value ? D + 1 : 1];
         if constexpr (PopDev<T>::value) {
           // store (g, M); the residual is then taken against the stored
           // output, so that the iterate of the stored iteration is what it
           // measures (and its fixed point has r = 0)
           T gq[Q];
-          float Mq[D + 1];
           dev_split<L, typename std::conditional<MODE == SW_EXPLICIT, float, double>::type>(vv, A.isig, gq, Mq);
 #pragma unroll
           for (int k = 0; k < Q; ++k) __builtin_nontemporal_store(gq[k], &dst[k * NS + site]);
@@ -776,6 +785,14 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
               if (ca<L>(k, bb) != 0) pr[1 + bb] += (CT)ca<L>(k, bb) * r;
             r2 += (double)r * (double)r;
           }
+        }
+        if constexpr (PopDev<T>::value && MODE != SW_EXPLICIT) {
+          // P r exactly: the stored output moments minus the trial's.  The
+          // rebuilt populations each carry FP32 rounding of about eps32 |f|,
+          // so their differences would put a floor of that size under P r,
+          // which the shadow solve amplifies by up to dt at small k.
+#pragma unroll
+          for (int bb = 0; bb <= D; ++bb) pr[bb] = (CT)((double)Mq[bb] - mprev[j][bb]);
         }
         if (MODE != SW_EXPLICIT) {
           if (ROWFFT && A.fuse_rows) {
@@ -813,6 +830,8 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
     for (int j = 0; j < SPT; ++j) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) fprev[j][k] = fcur[j][k];
+#pragma unroll
+      for (int b = 0; b < NMT; ++b) mprev[j][b] = mcur[j][b];
       c0prev[j] = c0c[j];
       cpx2[j] = cpx1[j];
       cpx1[j] = cpxc[j];
