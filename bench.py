@@ -1,17 +1,24 @@
 """Benchmark of the MSC-LBM dual-time march on one MI355X.
 
-Workload (default): D2Q9, N = 256, FP32 populations, divergence-free random
-initial velocity (seeded |k|^-3 stream function, |j| <= 16), Re = 1 at
-nu = 1/6, BDF2 dt = 256, horizon 0.25 N^2/nu = 98304 lattice steps (384
-physical steps).  A "step" is one physical BDF step: setup, the corrected
-inner iterations (sweep, residual, shadow correction) and acceptance.
+Workload (default): D3Q19, N = 128, FP64 populations and arithmetic (the
+paper's precision), 3D Taylor-Green vortex plus a seeded divergence-free
+perturbation (|k| <= 8, amplitude 1e-2 U), Re = 1 at nu = 1/6, BDF2 dt =
+63.83 (154 physical steps to the horizon 0.1 N^2/nu = 9830 lattice steps),
+n_min = 2, linear trial.  A "step" is one physical BDF step: setup, the
+corrected inner iterations (sweep, residual, shadow correction) and
+acceptance.  The tolerance is chosen by the paper's protocol: every candidate
+eps runs the full horizon, and the fastest passing both accuracy gates (the
+matched gate against the linear Stokes decay, and the 1% engineering gate
+against the FP64 explicit endpoint) is the one timed.
 
 Printed: one JSON line with wall-seconds per viscous time (N^2/nu lattice
-steps) of the corrected march, its speedup over the explicit TRT march run
-with the same sweep kernel on the same GPU over the same horizon, the
-accuracy of both against an FP64 explicit reference endpoint, the sweep
-kernel's achieved bandwidth from HIP events against the MI355X HBM peak, and
-the FP64 CPU oracle timed on a bounded sample on the host.
+steps) of the timed corrected march, the full-horizon speedup over the
+explicit TRT march (same sweep kernel, same GPU) under the gate that passed,
+the dominant kernel's achieved bandwidth from per-launch HIP events against
+the MI355X HBM peak, the FP64 CPU oracle timed on a bounded sample on the
+host, and the other workloads (FP32 3D, the 2D random fields at N = 256 and
+1024 in FP32 and FP16-deviation storage, the differentiable march, the
+paper's 2D Taylor-Green matched-gate cells at N = 256 ... 1024).
 """
 from __future__ import annotations
 
@@ -108,10 +115,19 @@ def sweep_beyond_cache(msc, stream, torch, NL=4096):
     }
 
 
-def counter_traffic(path=os.path.join(ROOT, "profiles", "hbm_traffic_sweep_d2q9_n256_fp32.md")):
-    """HBM bytes per sweep launch of the default workload from the committed
-    FETCH_SIZE/WRITE_SIZE summary, or None when the sweep kernel's sources
-    have changed since those counters were taken (or the summary is absent)."""
+def traffic_profile(workload):
+    """Committed counter summary of the dual-time sweep for a workload."""
+    name = {"tgv3d_n128_fp64": "hbm_traffic_sweep_d3q19_n128_fp64.md",
+            "rand2d_n256_fp32": "hbm_traffic_sweep_d2q9_n256_fp32.md"}.get(workload)
+    return os.path.join(ROOT, "profiles", name) if name else None
+
+
+def counter_traffic(path):
+    """HBM bytes per sweep launch from a committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the sweep kernel's sources have changed since those
+    counters were taken (or the summary is absent)."""
+    if path is None:
+        return None
     import hashlib
     try:
         fields = {}
@@ -141,14 +157,20 @@ def calibration_copies(torch):
     return a.numel() * 4
 
 
-def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=None):
+def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=None, dt=None):
     """Corrected march against the explicit march (same kernel, same storage)
     over the workload's whole horizon, both timed; accuracy against an FP64
-    explicit endpoint (cached per workload)."""
+    explicit endpoint (cached per workload) and against the linear Stokes
+    decay of the initial field (matched gate); the speedup is reported under
+    the gate that passed, or null."""
     cfg = W.config(name)
     N, nu, d = cfg["N"], cfg["nu"], cfg["d"]
     p0, u0 = W.initial_fields(cfg)
-    T_end, S, dt = cfg["T_end"], cfg["S"], cfg["dt"]
+    T_end = cfg["T_end"]
+    if dt is None:
+        S, dt = cfg["S"], cfg["dt"]
+    else:
+        S = int(round(T_end / dt))
     tnu = N * N / nu
 
     def solver(st, corrector, eps=cfg["eps"]):
@@ -160,7 +182,7 @@ def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=Non
         u_ref = ref_cache[name]
     else:
         r = solver("fp64", "picard")
-        r.explicit_step(int(T_end))
+        r.explicit_step(int(round(T_end)))
         u_ref = r.moments()[1:]
         r.close()
         if ref_cache is not None:
@@ -188,6 +210,11 @@ def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=Non
     iters = [x["iters"] for x in stats]
     e_msc = rms(u_msc - u_ref) / max(rms(u_ref), 1e-300)
     e_exp = rms(u_exp - u_ref) / max(rms(u_ref), 1e-300)
+    u_st = stokes_decay(u0, float(T_end), nu)
+    e_st, e_ref_st = rms(u_msc - u_st), rms(u_ref - u_st)
+    matched = rc == 0 and e_st <= 3.0 * e_ref_st
+    eng1 = rc == 0 and e_msc <= 1e-2
+    gate = "matched and 1%" if (matched and eng1) else ("1%" if eng1 else ("matched" if matched else None))
     Q = 9 if d == 2 else 19
     bsite = {"fp64": 16 * Q, "fp32": 8 * Q, "fp16dev": 4 * Q + 8 * (d + 1)}[storage]
     log(f"[bench] {name} {storage}: MSC {t_msc:.3f} s ({S} steps, inner {np.mean(iters):.2f}), explicit "
@@ -197,9 +224,11 @@ def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=Non
         "eps": cfg["eps"], "n_min": cfg["nmin"], "extrap_states": extrap, "physical_steps": S,
         "horizon_lattice_steps": T_end, "status": int(rc),
         "msc_wall_s_per_viscous_time": t_msc * tnu / T_end, "explicit_wall_s_per_viscous_time": t_exp * tnu / T_end,
-        "speedup_vs_explicit": t_exp / t_msc, "mean_inner": float(np.mean(iters)), "max_inner": int(max(iters)),
+        "speedup_vs_explicit": (t_exp / t_msc) if gate else None, "speedup_gate": gate,
+        "mean_inner": float(np.mean(iters)), "max_inner": int(max(iters)),
         "msc_rel_vs_fp64_explicit": e_msc, "explicit_rel_vs_fp64_explicit": e_exp,
-        "gate_1pct": e_msc <= 1e-2, "msc_not_less_accurate_than_explicit": e_msc <= e_exp,
+        "msc_abs_vs_stokes": e_st, "fp64_explicit_abs_vs_stokes": e_ref_st,
+        "gate_1pct": eng1, "gate_matched": matched, "msc_not_less_accurate_than_explicit": e_msc <= e_exp,
         "explicit_sweep_GBs": bsite * N ** d / (t_exp / T_end) / 1e9,
     }
 
@@ -253,6 +282,66 @@ def adjoint_workload(msc, W, stream, torch):
             "backward_over_forward": t_bwd / t_fwd,
             "note": "backward recomputes each step's inner iterates in FP64 from its checkpoint, then "
                     "runs the FP64 transposed sweeps and corrections"}
+
+
+def tgv_matched_cells(msc, W, stream, torch, cells=((256, 32, 1e-6, 0), (512, 64, 1e-6, 0), (1024, 256, 1e-8, 2)),
+                      reps=3):
+    """The paper's headline 2D comparison (Tab. tgv2d, matched gate) at N =
+    256, 512, 1024, Re = 1, FP64: the decaying Taylor-Green vortex over
+    T_end = nint(0.15 N^2); explicit march (minimum of two runs) against the
+    corrected march at the fastest passing (S, eps, trial rule) of the full
+    campaign (bench.py --tgv), re-timed here (minimum of reps runs) with the
+    gate e_abs <= 3 e_explicit re-evaluated against the analytic field."""
+    nu = 1.0 / 6.0
+    out = []
+    for N, S, eps, extrap in cells:
+        U = nu / N
+        T_end = W.nint(0.15 * N * N)
+        p0, u0 = W.tgv2d(N, U, nu)
+        _, u_an = W.tgv2d(N, U, nu, t=float(T_end))
+
+        def mk(corr, dt):
+            p = msc.make_params(2, N, dt=dt, eps=eps, storage="fp64", corrector=corr, n_min=2, k_max=300,
+                                extrap_states=extrap)
+            return msc.Solver(p, p0, u0, stream=stream)
+
+        t_exp = math.inf
+        for _ in range(2):
+            e = mk("picard", float(T_end))
+            e.explicit_step(64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e.explicit_step(T_end - 64)
+            torch.cuda.synchronize()
+            t_exp = min(t_exp, (time.perf_counter() - t0) * T_end / (T_end - 64))
+            u_exp = e.moments()[1:]
+            e.close()
+        e_exp = rms(u_exp - u_an)
+        w = mk("shadow", T_end / S)
+        w.bdf2_step(2, raise_on_fail=False)
+        w.close()
+        t_msc, rc, e_abs, inner = math.inf, 0, None, None
+        for _ in range(reps):
+            s = mk("shadow", T_end / S)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = s.bdf2_step(S, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if rc == 0:
+                t_msc = min(t_msc, t)
+                e_abs = rms(s.moments()[1:] - u_an)
+                inner = float(np.mean([x["iters"] for x in st]))
+            s.close()
+        passed = rc == 0 and e_abs is not None and e_abs <= 3.0 * e_exp
+        row = {"N": N, "Re": 1.0, "T_end": T_end, "S": S, "eps": eps,
+               "trial_rule": "paper" if extrap == 0 else f"{extrap} states", "explicit_s": t_exp, "msc_s": t_msc,
+               "explicit_e_abs": e_exp, "msc_e_abs": e_abs, "gate_matched": passed, "mean_inner": inner,
+               "S_wall": (t_exp / t_msc) if passed else None}
+        log(f"[tgv-matched] N={N}: explicit {t_exp:.4f} s, MSC {t_msc:.4f} s, e {e_abs} vs 3x{e_exp:.3e} "
+            f"-> S_wall {row['S_wall']}")
+        out.append(row)
+    return out
 
 
 def envelope(msc, W, stream, torch, N=128):
@@ -623,15 +712,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="physical steps timed (0: the whole horizon)")
     ap.add_argument("--warmup", type=int, default=8)
-    ap.add_argument("--workload", default="rand2d_n256_fp32")
-    ap.add_argument("--dt", type=float, default=256.0)
-    ap.add_argument("--eps", type=float, default=1e-8)
+    ap.add_argument("--workload", default="tgv3d_n128_fp64")
+    ap.add_argument("--dt", type=float, default=0.0, help="BDF step (0: the workload's)")
+    ap.add_argument("--eps-candidates", default="1e-6,1e-8,1e-10",
+                    help="candidate tolerances; the fastest passing both accuracy gates is timed")
     ap.add_argument("--extrap", type=int, default=2,
                     help="population states in the initial-trial extrapolation (0: paper rule, up to cubic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the beyond-cache sweep measurement")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the N=1024 (FP32, FP16 deviation) and D3Q19 N=128 workloads")
+                    help="skip the other workloads (FP32 3D, 2D N=256 and N=1024, adjoint, 2D matched-gate cells)")
     ap.add_argument("--march-only", action="store_true",
                     help="only the timed corrected march and its sweep timing pass (counter runs)")
     ap.add_argument("--envelope", action="store_true",
@@ -702,106 +792,154 @@ def main():
         return
     cfg = W.config(args.workload)
     N, nu, d = cfg["N"], cfg["nu"], cfg["d"]
-    shape = (N,) * d
-    dt = args.dt
+    dt = args.dt if args.dt > 0 else cfg["dt"]
     T_end = cfg["T_end"]
     S_full = int(round(T_end / dt))
+    T_full = S_full * dt
     K = args.steps if args.steps > 0 else S_full
-    T_sim = K * dt
     tnu = N * N / nu  # lattice steps per viscous time
     p0, u0 = W.initial_fields(cfg)
     storage = cfg["storage"]
-    dtype = {"fp64": "f64", "fp32": "f32"}[storage]
+    U = cfg["U"]
+    dtype = {"fp64": "f64", "fp32": "f32", "fp16dev": "f16dev"}[storage]
+    eps_list = [float(v) for v in args.eps_candidates.split(",")] if args.eps_candidates else [cfg["eps"]]
 
-    def solver(st=storage, corrector="shadow", eps=args.eps, ddt=dt, extrap=args.extrap):
-        p = msc.make_params(d, N, dt=ddt, eps=eps, storage=st, corrector=corrector, n_min=cfg["nmin"],
+    def solver(eps, st=storage, corrector="shadow", extrap=args.extrap):
+        p = msc.make_params(d, N, dt=dt, eps=eps, storage=st, corrector=corrector, n_min=cfg["nmin"],
                             extrap_states=extrap)
         return msc.Solver(p, p0, u0, stream=stream)
 
-    # ---- warmup (separate context; compiles nothing, fills caches/queues)
-    log(f"[bench] workload {args.workload} N={N} dt={dt} eps={args.eps} steps={K} warmup={args.warmup}")
-    s = solver()
-    s.bdf2_step(max(1, args.warmup))
-    s.explicit_step(128)
-    s.close()
+    def march(eps, steps, st=storage, extrap=args.extrap):
+        s = solver(eps, st, extrap=extrap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, stats = s.bdf2_step(steps, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        u = s.moments()[1:] if rc == 0 else None
+        s.close()
+        return int(rc), t, u, stats
 
-    # ---- timed corrected march
-    s = solver()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, stats = s.bdf2_step(K, raise_on_fail=False)
-    torch.cuda.synchronize()
-    t_msc = time.perf_counter() - t0
-    assert rc == 0, f"march failed: {rc}"
-    u_msc = s.moments()[1:]
-    iters = [st["iters"] for st in stats]
-    rhos = [st["rho_obs"] for st in stats if st["rho_obs"] == st["rho_obs"]]
-    s.close()
-    log(f"[bench] MSC: {t_msc:.3f} s for {K} steps, mean inner {np.mean(iters):.2f}")
-
-    # ---- roofline pass: same march with the sweep kernel bracketed by events
-    s = solver()
-    s.set_kernel_timing(True)
-    s.bdf2_step(K)
-    sec, launches, bytes_per = s.kernel_time(0)
-    s.close()
-    sweep_avg = sec / max(launches, 1)
-    sweep_gbs = bytes_per / sweep_avg / 1e9 if launches else float("nan")
-    log(f"[bench] sweep: {launches} launches, avg {sweep_avg * 1e6:.2f} us, {bytes_per / 1e6:.2f} MB -> {sweep_gbs:.0f} GB/s")
+    log(f"[bench] workload {args.workload} N={N} dt={dt:.4f} S={S_full} steps={K} warmup={args.warmup} "
+        f"eps candidates {eps_list}")
     if args.march_only:
-        part = {"workload": args.workload, "steps": K, "msc_s": t_msc, "sweep_launches": launches,
-                "sweep_avg_us": sweep_avg * 1e6, "sweep_bytes_per_launch": bytes_per}
+        # profiling runs: only the corrected march (first candidate eps), then
+        # the same steps with per-launch sweep timing
+        eps = eps_list[0]
+        s = solver(eps)
+        s.bdf2_step(max(1, args.warmup), raise_on_fail=False)
+        s.close()
+        rc, t_msc, _, stats = march(eps, K)
+        s = solver(eps)
+        s.set_kernel_timing(True)
+        s.bdf2_step(K, raise_on_fail=False)
+        sec, launches, bytes_per = s.kernel_time(0)
+        s.close()
+        part = {"workload": args.workload, "steps": K, "eps": eps, "status": rc, "msc_s": t_msc,
+                "mean_inner": float(np.mean([x["iters"] for x in stats])), "sweep_launches": launches,
+                "sweep_avg_us": sec / max(launches, 1) * 1e6, "sweep_bytes_per_launch": bytes_per}
         if args.calib:
             part["calibration_copy_bytes_each_way"] = calibration_copies(torch)
         print(json.dumps(part), flush=True)
         return
+    # ---- explicit march over the full horizon: the speedup baseline (same
+    # kernel, same storage) and, in FP64, the reference endpoint of the
+    # engineering gate
+    nexp = int(round(T_full))
+    t_exp = math.inf
+    for _ in range(2):
+        e = solver(cfg["eps"], corrector="picard")
+        e.explicit_step(64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.explicit_step(nexp - 64)
+        torch.cuda.synchronize()
+        t_exp = min(t_exp, (time.perf_counter() - t0) * nexp / (nexp - 64))
+        u_exp = e.moments()[1:]
+        e.close()
+    if storage == "fp64":
+        u_ref = u_exp
+    else:
+        r = solver(cfg["eps"], st="fp64", corrector="picard")
+        r.explicit_step(nexp)
+        u_ref = r.moments()[1:]
+        r.close()
+    u_stokes = stokes_decay(u0, T_full, nu)
+    e_exp_st = rms(u_ref - u_stokes)
 
-    # ---- explicit baseline: same sweep kernel, same storage, same horizon
-    nexp = int(round(T_sim))
-    e = solver(corrector="picard")
-    e.explicit_step(64)
-    e.close()
-    e = solver(corrector="picard")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e.explicit_step(nexp)
-    torch.cuda.synchronize()
-    t_exp = time.perf_counter() - t0
-    u_exp = e.moments()[1:]
+    def eng_err(u):
+        # 3D: RMS difference over U/2 (the paper's 3D engineering error);
+        # 2D: relative to the reference RMS
+        return rms(u - u_ref) / (U / 2) if d == 3 else rms(u - u_ref) / max(rms(u_ref), 1e-300)
+
+    log(f"[bench] explicit: {t_exp:.3f} s for {nexp} lattice steps; FP64 explicit vs Stokes {e_exp_st:.3e}")
+
+    # ---- tolerance by the paper's protocol (Sec. 4.1): every candidate eps
+    # over the full horizon, gates against the Stokes decay (matched) and the
+    # FP64 explicit endpoint (1%); the fastest candidate passing both is timed
+    w = solver(eps_list[0])
+    w.bdf2_step(2, raise_on_fail=False)
+    w.close()
+    cands = []
+    for eps in eps_list:
+        rc, t, u, st = march(eps, S_full)
+        c = {"eps": eps, "status": rc, "seconds": t,
+             "mean_inner": float(np.mean([x["iters"] for x in st])) if st else None}
+        if rc == 0:
+            c["e_vs_stokes"] = rms(u - u_stokes)
+            c["e_eng"] = eng_err(u)
+            c["gate_matched"] = c["e_vs_stokes"] <= 3.0 * e_exp_st
+            c["gate_1pct"] = c["e_eng"] <= 1e-2
+        else:
+            c.update({"gate_matched": False, "gate_1pct": False})
+        cands.append(c)
+        log(f"[bench] eps {eps:g}: status {rc} {t:.3f} s inner {c['mean_inner']} e_stokes "
+            f"{c.get('e_vs_stokes', float('nan')):.3e} e_eng {c.get('e_eng', float('nan')):.3e} "
+            f"matched {c['gate_matched']} 1% {c['gate_1pct']}")
+    passing = [c for c in cands if c["gate_matched"] and c["gate_1pct"]]
+    chosen = min(passing, key=lambda c: c["seconds"]) if passing else min(cands, key=lambda c: c["eps"])
+    eps = chosen["eps"]
+    rc, t2, _, _ = march(eps, S_full)
+    if rc == 0:
+        chosen["seconds"] = min(chosen["seconds"], t2)
+    gate = "matched and 1%" if passing else None
+
+    # ---- timed region: K physical steps from t = 0 after W warmup steps on
+    # a separate context
+    s = solver(eps)
+    s.bdf2_step(max(1, args.warmup), raise_on_fail=False)
+    s.close()
+    rc, t_msc, _, stats = march(eps, K)
+    assert rc == 0, f"march failed: {rc}"
+    iters = [x["iters"] for x in stats]
+    rhos = [x["rho_obs"] for x in stats if x["rho_obs"] == x["rho_obs"]]
+    log(f"[bench] timed MSC: {t_msc:.3f} s for {K} steps, mean inner {np.mean(iters):.2f}")
+
+    # ---- roofline pass: the same K steps with every sweep launch carrying
+    # its own start/stop events on the library's stream
+    s = solver(eps)
+    s.set_kernel_timing(True)
+    s.bdf2_step(K, raise_on_fail=False)
+    sec, launches, bytes_per = s.kernel_time(0)
+    s.close()
+    sweep_avg = sec / max(launches, 1)
+    sweep_gbs = bytes_per / sweep_avg / 1e9 if launches else float("nan")
+    log(f"[bench] sweep: {launches} launches, avg {sweep_avg * 1e6:.2f} us, {bytes_per / 1e6:.2f} MB -> "
+        f"{sweep_gbs:.0f} GB/s")
+    e = solver(eps, corrector="picard")
     e.set_kernel_timing(True)
-    e.explicit_step(256)
+    e.explicit_step(64)
     xsec, xl, xbytes = e.kernel_time(1)
     e.close()
-    log(f"[bench] explicit: {t_exp:.3f} s for {nexp} lattice steps; sweep avg {xsec / max(xl, 1) * 1e6:.2f} us")
 
-    # ---- the paper's extrapolation rule (up to cubic) on the same workload
-    s = solver(extrap=0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc0, st0 = s.bdf2_step(K, raise_on_fail=False)
-    torch.cuda.synchronize()
-    t_paper = time.perf_counter() - t0
-    s.close()
+    # ---- the paper's trial rule (up to cubic) on the same workload
+    rc0, t_paper, _, st0 = march(eps, S_full, extrap=0)
     done0 = sum(1 for x in st0 if x["converged"])
-    paper_rule = {"status": int(rc0), "steps_accepted": done0, "steps_requested": K, "seconds": t_paper,
-                  "mean_inner": float(np.mean([x["iters"] for x in st0[:max(done0, 1)]])),
-                  "last_iters": [x["iters"] for x in st0[max(0, done0 - 3):done0 + 1]]}
-    log(f"[bench] paper extrapolation rule: status {rc0}, {done0}/{K} steps accepted")
+    paper_rule = {"status": rc0, "steps_accepted": done0, "steps_requested": S_full, "seconds": t_paper,
+                  "mean_inner": float(np.mean([x["iters"] for x in st0[:max(done0, 1)]]))}
+    log(f"[bench] paper trial rule: status {rc0}, {done0}/{S_full} steps, {t_paper:.3f} s")
 
-    # ---- FP64 explicit reference endpoint and accuracy gates
-    r = solver(st="fp64", corrector="picard")
-    r.explicit_step(nexp)
-    u_ref = r.moments()[1:]
-    r.close()
-    u_stokes = stokes_decay(u0, T_sim, nu)
-    e_msc = rms(u_msc - u_ref) / max(rms(u_ref), 1e-300)
-    e_exp32 = rms(u_exp - u_ref) / max(rms(u_ref), 1e-300)
-    e_msc_st = rms(u_msc - u_stokes)
-    e_ref_st = rms(u_ref - u_stokes)
-    log(f"[bench] errors vs FP64 explicit: MSC {e_msc:.3e}, FP32 explicit {e_exp32:.3e}; vs Stokes: MSC {e_msc_st:.3e}, explicit {e_ref_st:.3e}")
-
-    value = t_msc * tnu / T_sim
-    value_exp = t_exp * tnu / T_sim
+    value = t_msc * tnu / (K * dt)
     out = {
         "metric": "wall-s per viscous time + speedup vs explicit TRT at matched err; HBM GB/s",
         "value": value,
@@ -816,28 +954,33 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": args.workload, "lattice": "D2Q9" if d == 2 else "D3Q19", "N": N, "Re": cfg["Re"],
-                   "nu": nu, "dt": dt, "eps": args.eps, "horizon_lattice_steps": T_sim,
-                   "viscous_times": T_sim / tnu, "storage": storage, "n_min": cfg["nmin"], "K_max": 300,
-                   "extrap_states": args.extrap},
-        "paper_extrapolation_rule": paper_rule,
-        "explicit_wall_s_per_viscous_time": value_exp,
-        "speedup_vs_explicit": t_exp / t_msc,
-        "accuracy": {"msc_rel_vs_fp64_explicit": e_msc, "fp32_explicit_rel_vs_fp64_explicit": e_exp32,
-                     "msc_abs_vs_stokes": e_msc_st, "fp64_explicit_abs_vs_stokes": e_ref_st,
-                     "gate_1pct": e_msc <= 1e-2, "gate_0p1pct": e_msc <= 1e-3,
-                     "gate_matched_vs_stokes": e_msc_st <= 3 * e_ref_st},
-        "inner_iterations": {"mean": float(np.mean(iters)), "max": int(max(iters)), "min": int(min(iters)),
-                             "rho_obs_median": float(np.median(rhos)) if rhos else None},
+                   "nu": nu, "dt": dt, "eps": eps, "physical_steps_timed": K, "physical_steps_horizon": S_full,
+                   "horizon_lattice_steps": T_full, "storage": storage, "n_min": cfg["nmin"], "K_max": 300,
+                   "extrap_states": args.extrap, "initial_field": cfg["kind"]},
+        "tolerance_selection": {"rule": "fastest candidate eps passing the matched and 1% gates over the full "
+                                        "horizon (Sec. 4.1 protocol)", "candidates": cands, "chosen": eps},
+        "full_horizon": {"msc_s": chosen["seconds"], "explicit_s": t_exp,
+                         "msc_wall_s_per_viscous_time": chosen["seconds"] * tnu / T_full,
+                         "explicit_wall_s_per_viscous_time": t_exp * tnu / T_full,
+                         "speedup_vs_explicit": (t_exp / chosen["seconds"]) if gate else None,
+                         "speedup_gate": gate, "mean_inner": chosen["mean_inner"],
+                         "msc_abs_vs_stokes": chosen.get("e_vs_stokes"), "fp64_explicit_abs_vs_stokes": e_exp_st,
+                         "msc_eng_err": chosen.get("e_eng"),
+                         "eng_err_definition": "RMS velocity difference from the FP64 explicit endpoint over U/2"
+                         if d == 3 else "RMS velocity difference from the FP64 explicit endpoint over its RMS"},
+        "paper_trial_rule": paper_rule,
+        "inner_iterations_timed": {"mean": float(np.mean(iters)), "max": int(max(iters)), "min": int(min(iters)),
+                                   "rho_obs_median": float(np.median(rhos)) if rhos else None},
         "roofline": {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sweep_gbs / HBM_PEAK_GBS,
-                     "traffic": counter_traffic() if args.workload == "rand2d_n256_fp32" else None,
-                     "kernel": "k_sweep (fused DTS sweep, lift + residual + P r)",
+                     "traffic": counter_traffic(traffic_profile(args.workload)),
+                     "kernel": "k_sweep (fused dual-time sweep: setup or lift, collision, streaming, residual, P r)",
                      "bytes_per_launch": bytes_per, "avg_launch_us": sweep_avg * 1e6, "launches": launches},
         "explicit_sweep": {"avg_launch_us": xsec / max(xl, 1) * 1e6, "bytes_per_launch": xbytes,
                            "achieved_GBs": xbytes / (xsec / max(xl, 1)) / 1e9 if xl else None},
     }
 
-    # ---- beyond-cache bandwidth: sweep kernel at N = 4096 (2 x 604 MB population arrays)
+    # ---- beyond-cache bandwidth of the sweep kernel
     if not args.no_large:
         out["sweep_beyond_cache"] = sweep_beyond_cache(msc, stream, torch)
         sb = out["sweep_beyond_cache"]
@@ -845,29 +988,35 @@ def main():
             f"{sb['dts']['achieved_GBs']:.0f} GB/s; D3Q19 N=256 explicit {sb['d3q19_n256_explicit']['achieved_GBs']:.0f}"
             f" GB/s; device copy {sb['device_copy']['achieved_GBs']:.0f} GB/s")
 
-    # ---- the other workloads of the method (speedup at matched accuracy)
+    # ---- the other workloads: the precision-policy lines, the paper's 2D
+    # matched-gate cells, and the differentiable march
     if not args.no_extras:
         cache = {}
-        out["workloads"] = {
-            "rand2d_n1024_fp32": extra_workload(msc, W, stream, torch, "rand2d_n1024_fp32", "fp32", ref_cache=cache),
-            "rand2d_n1024_fp16dev": extra_workload(msc, W, stream, torch, "rand2d_n1024_fp32", "fp16dev",
-                                                   ref_cache=cache),
-            "tgv3d_n128_fp32": extra_workload(msc, W, stream, torch, "tgv3d_n128_fp32", "fp32"),
-            "adjoint_vort2d_n256_fp32": adjoint_workload(msc, W, stream, torch),
-        }
-        out["full_symbol_reference"] = fullsym_cost(msc, W, stream, torch)
+        out["workloads"] = {}
+        if args.workload != "tgv3d_n128_fp32":
+            out["workloads"]["tgv3d_n128_fp32"] = extra_workload(msc, W, stream, torch, "tgv3d_n128_fp32", "fp32")
+        out["workloads"]["rand2d_n256_fp32_dt256"] = extra_workload(msc, W, stream, torch, "rand2d_n256_fp32",
+                                                                    "fp32", ref_cache=cache)
+        out["workloads"]["rand2d_n256_fp32_dt64"] = extra_workload(msc, W, stream, torch, "rand2d_n256_fp32", "fp32",
+                                                                   ref_cache=cache, dt=64.0)
+        out["workloads"]["rand2d_n1024_fp32"] = extra_workload(msc, W, stream, torch, "rand2d_n1024_fp32", "fp32",
+                                                               ref_cache=cache)
+        out["workloads"]["rand2d_n1024_fp16dev"] = extra_workload(msc, W, stream, torch, "rand2d_n1024_fp32",
+                                                                  "fp16dev", ref_cache=cache)
+        out["workloads"]["adjoint_vort2d_n256_fp32"] = adjoint_workload(msc, W, stream, torch)
+        out["tgv2d_matched_gate"] = tgv_matched_cells(msc, W, stream, torch)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload
     if not args.no_cpu_baseline:
         from oracle import oracle as orc  # the bench's CPU-baseline leg only
 
-        # step the oracle from t = 0 until about 12 s of CPU work
+        shape = (N,) * d
         st_, bc_ = orc.initial_state(p0, u0), 0
         its = []
         nsamp = 0
         t0 = time.perf_counter()
-        while nsamp < 2 or (time.perf_counter() - t0 < 12.0 and nsamp < K):
-            rc_, st_, bc_, sst = orc.march_state(st_, bc_, shape, dt=dt, nsteps=1, eps=args.eps, nmin=cfg["nmin"],
+        while nsamp < 1 or (time.perf_counter() - t0 < 12.0 and nsamp < K):
+            rc_, st_, bc_, sst = orc.march_state(st_, bc_, shape, dt=dt, nsteps=1, eps=eps, nmin=cfg["nmin"],
                                                  extrap_states=args.extrap)
             its.append(sst[0]["iters"])
             nsamp += 1
@@ -876,8 +1025,8 @@ def main():
         out["cpu_baseline"] = {
             "value": per_step * tnu / dt, "unit": out["unit"].replace("corrected BDF2 march", "FP64 oracle march"),
             "cores": 1, "kind": "oracle",
-            "sample": f"{nsamp} physical BDF steps (dt={dt}) of the same N={N} workload from t=0, "
-                      f"{t_cpu:.1f} s, scaled per step to one viscous time",
+            "sample": f"{nsamp} physical BDF step(s) (dt={dt:.3f}, eps={eps:g}) of the same N={N} workload from "
+                      f"t=0, {t_cpu:.1f} s, scaled per step to one viscous time",
             "host": platform.processor() or platform.machine(), "host_nproc": os.cpu_count(),
             "mean_inner_iterations": float(np.mean(its)),
         }
@@ -887,7 +1036,6 @@ def main():
         out["calibration_copy_bytes_each_way"] = calibration_copies(torch)
 
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()
