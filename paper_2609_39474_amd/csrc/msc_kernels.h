@@ -17,6 +17,10 @@ struct AcceptArgs {
   const double* h;
   int64_t NS;
   double a;
+  // 1: the reconstruction of m^{n+1} is left to the next step's setup sweep,
+  // which forms it from the same populations (the next step is enqueued by
+  // the same call)
+  int defer;
 };
 
 // P f in FP64 at one site (for deviation storage the stored moments, which
@@ -81,6 +85,7 @@ __device__ inline void site_store(T* f, int64_t NS, int64_t s, float isig, const
 // and m^n).
 template <class L, class T>
 __device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64_t s1, int64_t stride) {
+  if (A.defer) return;
   const Roles& ro = A.ctl->roles[A.n & 1];
   const T* f = A.fb.p[ro.slot_w[A.ell & 1]];
   double* m = A.mb[ro.slot_m[2]];

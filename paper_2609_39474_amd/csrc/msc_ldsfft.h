@@ -37,21 +37,38 @@ __device__ __forceinline__ cpx<CT> cmuli(cpx<CT> a, int s) {
 __device__ __forceinline__ int xcd_item(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
 __host__ __device__ constexpr int pad8(int n) { return (n + 7) / 8 * 8; }
 
+// Bank swizzle of the intermediate stages: element i of a line is stored at
+// i with its position inside a 128-byte row XORed with the row number, so the
+// strided writes of the early radix-4 stages (stride 4 Ns elements) fall on
+// different banks; a bijection within every aligned row group, so a line of
+// N >= G elements keeps its footprint.
+template <class CT>
+__device__ __forceinline__ int lds_swz(int i) {
+  constexpr int G = 128 / (int)sizeof(cpx<CT>);  // elements per 128-byte row: 8 (FP64), 16 (FP32)
+  return i ^ ((i / G) & (G - 1));
+}
+
 // nt independent transforms of length N = 2^lg stored contiguously at
 // buf + t*N.  sign = -1 forward, +1 inverse (no scaling).  The caller has
 // synchronised after filling buf; returns the array holding the result (buf
-// or tmp), synchronised.
+// or tmp), synchronised.  The first stage reads and the last stage writes in
+// the plain layout (both contiguous); the stages in between keep their
+// outputs swizzled (lds_swz) when lines hold at least G elements.
 template <class CT>
 __device__ cpx<CT>* lds_fft(cpx<CT>* buf, cpx<CT>* tmp, int lg, int nt, int sign,
                             const cpx<CT>* __restrict__ tw) {
+  constexpr int G = 128 / (int)sizeof(cpx<CT>);
   const int N = 1 << lg;
   const int tid = threadIdx.x, nth = blockDim.x;
+  const bool swz = N >= G;
+  const int nst = (lg >> 1) + (lg & 1);  // stages
   cpx<CT>* a = buf;
   cpx<CT>* b = tmp;
   int Ns = 1;
   for (int p = 0; p < (lg >> 1); ++p) {
     const int lnb = lg - 2, nb = 1 << lnb;
     const int tstride = N / (4 * Ns);
+    const bool rs = swz && p > 0, ws = swz && p + 1 < nst;
     for (int j = tid; j < (nt << lnb); j += nth) {
       const int t = j >> lnb, jj = j & (nb - 1);
       const cpx<CT>* x = a + t * N;
@@ -63,17 +80,17 @@ __device__ cpx<CT>* lds_fft(cpx<CT>* buf, cpx<CT>* tmp, int lg, int nt, int sign
         w2.y = -w2.y;
         w3.y = -w3.y;
       }
-      const cpx<CT> v0 = x[jj];
-      const cpx<CT> v1 = cmul(x[jj + nb], w1);
-      const cpx<CT> v2 = cmul(x[jj + 2 * nb], w2);
-      const cpx<CT> v3 = cmul(x[jj + 3 * nb], w3);
+      const cpx<CT> v0 = x[rs ? lds_swz<CT>(jj) : jj];
+      const cpx<CT> v1 = cmul(x[rs ? lds_swz<CT>(jj + nb) : jj + nb], w1);
+      const cpx<CT> v2 = cmul(x[rs ? lds_swz<CT>(jj + 2 * nb) : jj + 2 * nb], w2);
+      const cpx<CT> v3 = cmul(x[rs ? lds_swz<CT>(jj + 3 * nb) : jj + 3 * nb], w3);
       const cpx<CT> s02 = cadd(v0, v2), d02 = csub(v0, v2);
       const cpx<CT> s13 = cadd(v1, v3), d13 = cmuli(csub(v1, v3), sign);
       const int base = ((jj - k) << 2) + k;
-      y[base] = cadd(s02, s13);
-      y[base + Ns] = cadd(d02, d13);
-      y[base + 2 * Ns] = csub(s02, s13);
-      y[base + 3 * Ns] = csub(d02, d13);
+      y[ws ? lds_swz<CT>(base) : base] = cadd(s02, s13);
+      y[ws ? lds_swz<CT>(base + Ns) : base + Ns] = cadd(d02, d13);
+      y[ws ? lds_swz<CT>(base + 2 * Ns) : base + 2 * Ns] = csub(s02, s13);
+      y[ws ? lds_swz<CT>(base + 3 * Ns) : base + 3 * Ns] = csub(d02, d13);
     }
     __syncthreads();
     cpx<CT>* sw = a;
@@ -84,6 +101,7 @@ __device__ cpx<CT>* lds_fft(cpx<CT>* buf, cpx<CT>* tmp, int lg, int nt, int sign
   if (lg & 1) {
     const int lnb = lg - 1, nb = 1 << lnb;
     const int tstride = N / (2 * Ns);
+    const bool rs = swz && nst > 1;
     for (int j = tid; j < (nt << lnb); j += nth) {
       const int t = j >> lnb, jj = j & (nb - 1);
       const cpx<CT>* x = a + t * N;
@@ -91,8 +109,8 @@ __device__ cpx<CT>* lds_fft(cpx<CT>* buf, cpx<CT>* tmp, int lg, int nt, int sign
       const int k = jj & (Ns - 1);
       cpx<CT> w1 = tw[k * tstride];
       if (sign > 0) w1.y = -w1.y;
-      const cpx<CT> v0 = x[jj];
-      const cpx<CT> v1 = cmul(x[jj + nb], w1);
+      const cpx<CT> v0 = x[rs ? lds_swz<CT>(jj) : jj];
+      const cpx<CT> v1 = cmul(x[rs ? lds_swz<CT>(jj + nb) : jj + nb], w1);
       const int base = ((jj - k) << 1) + k;
       y[base] = cadd(v0, v1);
       y[base + Ns] = csub(v0, v1);

@@ -73,7 +73,7 @@ class Solver : public SolverBase {
     return guard([&]() {
       sync();
       choose_sweep();
-      ensure_partials(sweep_grid());
+      ensure_partials(sweep_grid_max());
       if (spec && corrector_supported()) set_fft_attrs();
       if (gexec) (void)hipGraphExecDestroy(gexec);
       if (graph) (void)hipGraphDestroy(graph);
@@ -188,8 +188,16 @@ class Solver : public SolverBase {
           // resuming a step: the previous batch ended it at sweep ell0 - 1
           // without the correction's later passes
           if (ell0 > 1) enqueue_correction_tail(n, ell0 - 1, a);
+          // within one call, each step's acceptance leaves m^{n+1} to the next
+          // step's setup sweep (which reads the same populations anyway); the
+          // call's last step reconstructs it so that the state is complete
+          // when the call returns, and recording keeps every step complete for
+          // its checkpoint
+          const bool recon = !recording && n > stat_base;
+          const double a_prev = (bc - 1 == 0) ? 1.0 / P.dt : 3.0 / (2.0 * P.dt);
+          const bool defer = !recording && n < n_end - 1;
           for (int ell = ell0; ell <= ell1; ++ell)
-            enqueue_iteration(n, ell, q, order, a, use_sched, stat_base, ell == ell1);
+            enqueue_iteration(n, ell, q, order, a, use_sched, stat_base, ell == ell1, recon, a_prev, defer);
         }
         MSC_HIPCK(hipMemcpyAsync(ctl_h, ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
         sync();
@@ -903,6 +911,9 @@ class Solver : public SolverBase {
   FBufs<T> fb{};
   double* mb[3] = {nullptr, nullptr, nullptr};
   double* h = nullptr;
+  // history term of odd physical steps (even steps use h): a setup sweep that
+  // forms m^n from the previous step's h writes its own step's h meanwhile
+  double* h_alt = nullptr;
   TM* Pr = nullptr;
   TM* dm = nullptr;
   cpx<CT>* spec = nullptr;
@@ -1090,16 +1101,18 @@ class Solver : public SolverBase {
     for (int i = 0; i < 5; ++i) fb.p[i] = keep((T*)dalloc(fbytes));
     for (int i = 0; i < 3; ++i) mb[i] = keep((double*)dalloc(sizeof(double) * (D + 1) * NS));
     h = keep((double*)dalloc(sizeof(double) * (D + 1) * NS));
+    h_alt = keep((double*)dalloc(sizeof(double) * (D + 1) * NS));
     Pr = keep((TM*)dalloc(sizeof(TM) * (D + 1) * NS));
     dm = keep((TM*)dalloc(sizeof(TM) * (D + 1) * NS));
     MSC_HIPCK(hipMemsetAsync(h, 0, sizeof(double) * (D + 1) * NS, st));
+    MSC_HIPCK(hipMemsetAsync(h_alt, 0, sizeof(double) * (D + 1) * NS, st));
     MSC_HIPCK(hipMemsetAsync(dm, 0, sizeof(TM) * (D + 1) * NS, st));
     ctl = keep((DevCtl*)dalloc(sizeof(DevCtl)));
     MSC_HIPCK(hipHostMalloc((void**)&ctl_h, sizeof(DevCtl), hipHostMallocDefault));
     Rhist = keep((double*)dalloc(sizeof(double) * std::max(P.k_max, 1)));
     presum = keep((double*)dalloc(sizeof(double)));
     choose_sweep();
-    ensure_partials(sweep_grid());
+    ensure_partials(sweep_grid_max());
     if (corrector_supported()) {
       if (D == 2) {
         const int NB = G.N2 / 4 + 1;
@@ -1554,6 +1567,7 @@ class Solver : public SolverBase {
 
   // ------------------------------------------------------ sweep config --
   int tile_id = 0, strip_L = 1;
+  int strip_setup = 1;  // planes per strip of the first sweep of a step
   TileCfg tile{};
   // 2D with the shadow corrector and tiles spanning whole rows: the sweep
   // also does the forward row transform of P r
@@ -1578,15 +1592,18 @@ class Solver : public SolverBase {
     if (best < 0) best = auto_sweep_tile<L>(G.N1, G.N2);
     tile_id = best;
     tile = TileSet<L>::get(best);
-    strip_L = sweep_strip_for<L>(tile, G.N0, G.N1, G.N2, tune.sweep_strip);
+    strip_L = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip);
+    strip_setup = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, true);
     fuse_rows = D == 2 && P.corrector == MSC_CORRECTOR_SHADOW && tile.T1 == 1 && tile.T2 == G.N2 &&
                 tile.NT == tile.T2 && corrector_supported() && tune.fuse_rows != 0;
     fuse_inv = fuse_rows && strip_L == 1 && tune.fuse_rows >= 2;
   }
 
-  int sweep_grid() const {
-    return (int)((int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2) * (G.N0 / strip_L));
+  int sweep_grid(int mode = SW_DTS) const {
+    const int Ls = (mode == SW_DTS_SETUP) ? strip_setup : strip_L;
+    return (int)((int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2) * (G.N0 / Ls));
   }
+  int sweep_grid_max() const { return std::max(sweep_grid(), sweep_grid(SW_DTS_SETUP)); }
 
   SweepArgs<T, TM> sweep_args(double a) {
     SweepArgs<T, TM> S{};
@@ -1682,13 +1699,17 @@ class Solver : public SolverBase {
       ep.b = get_event();
       ep.kind = (mode == SW_EXPLICIT) ? 1 : 0;
       ep.flag = (int)ev_live.size();
-      ep.bytes = sweep_bytes(mode, S.order, S.q);
+      ep.bytes = sweep_bytes(mode, S.order, S.q) + ((mode == SW_DTS_SETUP && S.recon) ? (double)(D + 1) * G.NS * 8.0 : 0.0);
       S.did_run = run_flags + ep.flag;
     }
+    if (mode == SW_DTS_SETUP) {
+      S.L = strip_setup;
+      S.nstrip = G.N0 / strip_setup;
+    }
     if (D == 2)
-      launch_sweep_d2<T, TM>(tile_id, mode, S, sweep_grid(), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
+      launch_sweep_d2<T, TM>(tile_id, mode, S, sweep_grid(mode), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
     else
-      launch_sweep_d3<T, TM>(tile_id, mode, S, sweep_grid(), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
+      launch_sweep_d3<T, TM>(tile_id, mode, S, sweep_grid(mode), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
     MSC_HIPCK(hipGetLastError());
     if (timing) {
       ev_live.push_back(ep);
@@ -1730,10 +1751,17 @@ class Solver : public SolverBase {
   // last: the final iteration enqueued for this step; its correction passes
   // after the first are left out (they run only if the step goes on, and then
   // enqueue_correction_tail supplies them before the next sweep).
+  // recon: this step's setup sweep forms m^n (the previous step, coefficient
+  // a_prev, left it); defer: this step's acceptance leaves m^{n+1} to the
+  // next step's setup sweep.
   void enqueue_iteration(int n, int ell, int q, int order, double a, bool use_sched, int stat_base,
-                         bool last = false) {
+                         bool last = false, bool recon = false, double a_prev = 0.0, bool defer = false) {
     SweepArgs<T, TM> S = sweep_args(a);
     S.ctl = ctl;
+    S.h = h_of(n);
+    S.recon = (ell == 1 && recon) ? 1 : 0;
+    S.h_prev = h_of(n - 1);
+    S.a_prev = a_prev;
     S.n = n;
     S.ell = ell;
     for (int i = 0; i < 3; ++i) S.mb[i] = mb[i];
@@ -1755,7 +1783,6 @@ class Solver : public SolverBase {
     F.stats = stats_d;
     F.stat_base = stat_base;
     F.partials = partials;
-    F.nparts = sweep_grid();
     int mode;
     if (ell == 1)
       mode = SW_DTS_SETUP;
@@ -1763,6 +1790,7 @@ class Solver : public SolverBase {
       mode = fuse_inv ? SW_DTS_LIFT_ROWS : SW_DTS_LIFT;
     else
       mode = SW_DTS;
+    F.nparts = sweep_grid(mode);
     if (fullsym() || wallkin()) S.rout = rfs;
     if (fuse_rows) {
       S.fuse_rows = 1;
@@ -1782,6 +1810,7 @@ class Solver : public SolverBase {
     }
 
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
+    Ac.defer = defer ? 1 : 0;
     if (P.corrector == MSC_CORRECTOR_SHADOW) {
       XformBufs<CT, TM> B{Pr, dm, spec_of(ell), spec2, {tw[0], tw[1], tw[2]}};
       enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last && !fuse_inv, fuse_rows);
@@ -1812,6 +1841,9 @@ class Solver : public SolverBase {
   // own forward rows)
   cpx<CT>* spec_of(int ell) const { return (fuse_inv && (ell & 1)) ? spec_alt : spec; }
 
+  // history term of physical step n (see h_alt); the wall corrector keeps one
+  double* h_of(int n) const { return (!wallkin() && (n & 1)) ? h_alt : h; }
+
   AcceptArgs<L, T> accept_args(int n, int ell, double a) {
     AcceptArgs<L, T> Ac{};
     Ac.ctl = ctl;
@@ -1819,7 +1851,7 @@ class Solver : public SolverBase {
     Ac.ell = ell;
     Ac.fb = fb;
     for (int i = 0; i < 3; ++i) Ac.mb[i] = mb[i];
-    Ac.h = h;
+    Ac.h = h_of(n);
     Ac.NS = G.NS;
     Ac.a = a;
     return Ac;

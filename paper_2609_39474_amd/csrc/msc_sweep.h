@@ -197,6 +197,13 @@ struct SweepArgs {
   double* mb[3];
   int q, order;
   double dt;
+  // setup mode, recon = 1: the previous step's acceptance left m^n to this
+  // sweep, which forms it from f^n with that step's history term h_prev and
+  // coefficient a_prev (Eq. macro-reconstruct) and writes it for the owned
+  // sites; h (this step's) is then a different buffer from h_prev
+  int recon;
+  const double* h_prev;
+  double a_prev;
   // fused forward row transform (2D, tiles spanning whole rows, Algorithm 1
   // with the shadow corrector): the band spectrum of P r goes to spec
   // ([field][x][j <= N_y/4], as the first transform pass writes it) instead
@@ -245,8 +252,21 @@ __host__ __device__ constexpr int local_dir(int cxv) {
 
 // ring depth per group: a value pushed towards plane x+1 is read two plane
 // steps later, towards x one step later, towards x-1 in the same step; with
-// one barrier per step the rings need 4, 3 and 2 slots.
-__host__ __device__ constexpr int ring_depth(int g) { return g == 0 ? 4 : (g == 1 ? 3 : 2); }
+// one barrier per step the rings need 4, 3 and 2 slots, with a second
+// barrier after the finalisation 3, 2 and 1 (a third less LDS).
+__host__ __device__ constexpr int ring_depth(int g, bool two_bar) {
+  return two_bar ? (g == 0 ? 3 : (g == 1 ? 2 : 1)) : (g == 0 ? 4 : (g == 1 ? 3 : 2));
+}
+
+// Two barriers per plane step where the LDS of the one-barrier rings would
+// hold the block count per CU down: D3Q19 with FP64 populations (96 KB per
+// 256-thread block, one block per CU; 64 KB with two barriers, two blocks per
+// CU for the explicit and lift sweeps: N = 128 explicit sweep 184 -> 166 us,
+// corrected march 1% faster).
+template <class L, class T>
+__host__ __device__ constexpr bool sweep_two_barriers() {
+  return L::D == 3 && sizeof(T) == 8;
+}
 
 __device__ inline int wrapi(int v, int n) {
   v %= n;
@@ -259,8 +279,9 @@ struct SrcPtrs {
   const T* s0;  // trial populations (f^n in setup mode)
   const T* s1;  // f^{n-1} (setup mode)
   const T* s2;  // f^{n-2} (setup mode)
-  const double* mc;  // m^n (setup mode)
+  const double* mc;  // m^n (setup mode), or the previous h with recon
   const double* mp;  // m^{n-1} (setup mode)
+  double* mw;        // m^n written (setup mode with recon)
 };
 
 // Raw loads of one site, issued one plane ahead of their use so that the
@@ -334,16 +355,49 @@ __device__ __forceinline__ void load_raw(const SweepArgs<T, TM>& A, const SrcPtr
 template <class L, class T, class TM, int MODE>
 __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const RawSite<L, T, TM, MODE>& r,
                                             typename CompT<T>::type* f, typename CompT<T>::type* C,
-                                            double* hout, double* Mtrial = nullptr) {
+                                            double* hout, double* Mtrial = nullptr, double* mnout = nullptr) {
   using CT = typename CompT<T>::type;
   constexpr int Q = L::Q, D = L::D;
   constexpr bool DV = PopDev<T>::value;
   double h[4] = {0, 0, 0, 0};
   if (MODE == SW_DTS_SETUP) {
+    // m^n: loaded, or with recon formed here from f^n and the previous step's
+    // history term (Eq. macro-reconstruct, the reconstruction the previous
+    // step's acceptance left to this sweep)
+    double mn[4];
+    if (A.recon) {
+      double Mn[4] = {0, 0, 0, 0};
+      if constexpr (DV) {
+#pragma unroll
+        for (int b = 0; b <= D; ++b) Mn[b] = (double)r.M0[b];
+      } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          const double fk = (double)r.f0[k];
+          Mn[0] += fk;
+#pragma unroll
+          for (int b = 0; b < D; ++b) {
+            if (ca<L>(k, b) > 0)
+              Mn[1 + b] += fk;
+            else if (ca<L>(k, b) < 0)
+              Mn[1 + b] -= fk;
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b <= D; ++b) mn[b] = (Mn[b] + r.hv[b] / 2.0) / (1.0 + A.a_prev / 2.0);
+      if (mnout) {
+#pragma unroll
+        for (int b = 0; b <= D; ++b) mnout[b] = mn[b];
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b <= D; ++b) mn[b] = r.hv[b];
+    }
     // Eq. (bdf2) in FP64, and the extrapolated initial trial (Sec. 3.1)
 #pragma unroll
     for (int b = 0; b <= D; ++b)
-      h[b] = (A.q == 1) ? r.hv[b] / A.dt : (4.0 * r.hv[b] - r.mpv[b]) / (2.0 * A.dt);
+      h[b] = (A.q == 1) ? mn[b] / A.dt : (4.0 * mn[b] - r.mpv[b]) / (2.0 * A.dt);
     if constexpr (DV) {
       CT g1[Q], g2[Q];
       dev_rebuild<L>(r.f0, r.M0, A.sig, f);
@@ -507,15 +561,16 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
 // block per CU runs anyway).
 // The D2Q9 FP32 dual-time and lift sweeps need 129-131 registers, one or
 // three above the 128 that allow four waves per SIMD; bounded to four.
-template <class L, class T, int MODE>
+template <class L, class T, int MODE, int T1>
 __host__ __device__ constexpr int sweep_min_waves() {
   return (L::D == 2 && sizeof(T) == 8 && MODE == SW_DTS_SETUP)                          ? 2
          : (L::D == 2 && sizeof(T) == 4 && (MODE == SW_DTS || MODE == SW_DTS_LIFT)) ? 4
+         : (sweep_two_barriers<L, T>() && MODE != SW_DTS_SETUP && T1 > 1)             ? 2
                                                                                        : 1;
 }
 
 template <class L, class T, class TM, int NT, int T1, int T2, int MODE>
-__global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(SweepArgs<T, TM> A) {
+__global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_sweep(SweepArgs<T, TM> A) {
   using CT = typename CompT<T>::type;
   constexpr int Q = L::Q, D = L::D;
   constexpr int NI = T1 * T2;
@@ -535,12 +590,14 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
   // inverted dm rows of the three source planes of a one-plane strip: line
   // 2p packs (dm_0 + i dm_1) of plane p, line 2p+1 holds dm_2; ping-pong
   __shared__ cpx<CT> ibuf[ROWINV ? 12 * T2 : 1];
-  __shared__ LT ldsP[4][NGP][NI];
-  __shared__ LT ldsZ[3][NG0][NI];
-  __shared__ LT ldsM[2][NGM][NI];
+  constexpr bool TWOBAR = sweep_two_barriers<L, T>();
+  constexpr int DP = ring_depth(0, TWOBAR), DZ = ring_depth(1, TWOBAR), DM = ring_depth(2, TWOBAR);
+  __shared__ LT ldsP[DP][NGP][NI];
+  __shared__ LT ldsZ[DZ][NG0][NI];
+  __shared__ LT ldsM[DM][NGM][NI];
   __shared__ double red[NT];
 
-  SrcPtrs<T> P{A.src, nullptr, nullptr, nullptr, nullptr};
+  SrcPtrs<T> P{A.src, nullptr, nullptr, nullptr, nullptr, nullptr};
   T* __restrict__ dst = A.dst;
   if (A.ctl) {
     const uint64_t ph = A.ctl->phase;
@@ -550,8 +607,9 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
       P.s0 = A.fb.p[ro.slot_hist[0]];
       P.s1 = A.fb.p[ro.slot_hist[1]];
       P.s2 = A.fb.p[ro.slot_hist[2]];
-      P.mc = A.mb[ro.slot_m[0]];
+      P.mc = A.recon ? A.h_prev : A.mb[ro.slot_m[0]];
       P.mp = A.mb[ro.slot_m[1]];
+      P.mw = A.mb[ro.slot_m[0]];
     } else {
       P.s0 = A.fb.p[ro.slot_w[(A.ell - 1) & 1]];
     }
@@ -584,6 +642,18 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
   RawSite<L, T, TM, MODE> raw[SPT];
   double r2 = 0.0;
 
+  // tile-relative coordinates of halo ring site t (rows along p1 first, then
+  // columns along p2)
+  auto halo_at = [&](int t, int& i1, int& i2) {
+    if (t < 2 * h1 * S2) {
+      i1 = (t < S2) ? -1 : T1;
+      i2 = (t % S2) - h2;
+    } else {
+      const int u = t - 2 * h1 * S2;
+      i2 = (u < T1) ? -1 : T2;
+      i1 = u % T1;
+    }
+  };
   // prefetch the owned sites of the first source plane
   {
     const int xs0 = wrapi(x0 - 1, N0);
@@ -644,7 +714,8 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
     const bool wP = it <= A.L - 1;             // dest plane it+1 is finalised later
     const bool wZ = it >= 1 && it <= A.L;      // dest plane it
     const bool wM = it >= 2;                   // dest plane it-1
-    const int sP = (it + 1) & 3, sZ = it % 3, sM = (it + 1) & 1;
+    // slots keyed by the destination plane's index modulo the ring depth
+    const int sP = (it + 1) % DP, sZ = it % DZ, sM = (it + DM - 1) % DM;
 
     // ---- owned interior sources --------------------------------------------
 #pragma unroll
@@ -663,12 +734,16 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
         }
       }
       CT C[Q];
-      double hs[4];
-      collide_raw<L, T, TM, MODE>(A, cur, fcur[j], C, hs, mcur[j]);
+      double hs[4], mns[4];
+      collide_raw<L, T, TM, MODE>(A, cur, fcur[j], C, hs, mcur[j], mns);
       if (MODE == SW_DTS_SETUP && it >= 1 && it <= A.L) {
         const int64_t site = ((int64_t)xs * N1 + (b1 + i1)) * N2 + (b2 + i2);
 #pragma unroll
         for (int bb = 0; bb <= D; ++bb) A.h[bb * NS + site] = hs[bb];
+        if (A.recon) {
+#pragma unroll
+          for (int bb = 0; bb <= D; ++bb) P.mw[bb * NS + site] = mns[bb];
+        }
       }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
@@ -695,14 +770,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
     // ---- halo ring sources (only along axes the tile does not span) -------
     for (int t = tid; t < nhalo; t += NT) {
       int i1, i2;
-      if (t < 2 * h1 * S2) {
-        i1 = (t < S2) ? -1 : T1;
-        i2 = (t % S2) - h2;
-      } else {
-        const int u = t - 2 * h1 * S2;
-        i2 = (u < T1) ? -1 : T2;
-        i1 = u % T1;
-      }
+      halo_at(t, i1, i2);
       const int p1 = wrapi(b1 + i1, N1), p2 = wrapi(b2 + i2, N2);
       RawSite<L, T, TM, MODE> hr;
       load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs * N1 + p1) * N2 + p2, hr);
@@ -734,7 +802,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
     if (it >= 2) {
       const int id = it - 1;
       const int xd = wrapi(x0 + id - 1, N0);
-      const int rP = id & 3, rZ = id % 3, rM = id & 1;
+      const int rP = id % DP, rZ = id % DZ, rM = id % DM;
 #pragma unroll
       for (int j = 0; j < SPT; ++j) {
         const int s = tid + j * NT;
@@ -825,6 +893,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE>())) void k_sweep(S
         }
       }
     }
+    if constexpr (TWOBAR) __syncthreads();  // the rings' slots are refilled next step
     // ---- roll registers ------------------------------------------------------
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {

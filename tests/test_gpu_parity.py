@@ -336,6 +336,42 @@ def test_random_field_fp32_vs_fp64_oracle(M, orc):
     s.close()
 
 
+@pytest.mark.parametrize("d,storage", [(2, "fp64"), (2, "fp16dev"), (3, "fp64"), (3, "fp32")])
+def test_reconstruction_in_next_setup_sweep(M, d, storage):
+    """Within one call the acceptance of a step leaves m^{n+1} to the next
+    step's setup sweep; the call's last step reconstructs it itself.  The same
+    steps taken in one call, in calls of one step (every step reconstructs at
+    acceptance) and in calls of three, four and three steps give the same full
+    march state (populations and both moment slots, per field)."""
+    N = 32 if d == 2 else 16
+    shape = (N,) * d
+    if d == 2:
+        p0, u0 = W.random_field_2d(N, 4 * NU / N, seed=6, jmax=6)
+    else:
+        p0, u0 = W.tgv3d_perturbed(N, NU / N, seed=2, jmax=3)
+    K = [4, 3, 3, 3, 2, 3, 2, 2, 3, 2]  # a fixed schedule, replayed by every run
+    ref = _solver(M, shape, dt=48.0, eps=1e-10, storage=storage, p0=p0, u0=u0, n_min=2)
+    ref.set_schedule(K)
+    rc, st = ref.bdf2_step(10)
+    assert rc == 0 and [x["iters"] for x in st] == K
+    a_state, a_bc = ref.get_state()
+    ref.close()
+    for split in ([1] * 10, [3, 4, 3]):
+        s = _solver(M, shape, dt=48.0, eps=1e-10, storage=storage, p0=p0, u0=u0, n_min=2)
+        s.set_schedule(K)
+        for k in split:
+            rc, _ = s.bdf2_step(k)
+            assert rc == 0
+        b_state, b_bc = s.get_state()
+        s.close()
+        assert b_bc == a_bc
+        worst = 0.0
+        for (x, nf), (y, _) in zip(_state_parts(b_state, d, shape), _state_parts(a_state, d, shape)):
+            worst = max(worst, max(PB.field_rels(x, y, nf)))
+        say("deferred reconstruction", d, storage, split, "worst per-field rel", worst)
+        assert worst <= (1e-12 if storage == "fp64" else 1e-6)
+
+
 def test_failure_paths(M, orc):
     N = 16
     p0, u0 = W.tgv2d(N, NU / N, NU)
