@@ -37,6 +37,7 @@ struct Tuning {
   int fft3_cols = 0;         // 3D transform passes: j_z columns per block, 0 = automatic
   int fs_split = 0;          // full-symbol column pass: 0 = automatic, 1 = three kernels
                              // (transforms, solve, transforms), 2 = one fused kernel
+  int explicit_aa = 1;       // explicit march in place by the AA pattern where available
 };
 
 class SolverBase {

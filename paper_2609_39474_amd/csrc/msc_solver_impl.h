@@ -12,6 +12,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "msc_aa.h"
 #include "msc_adjoint.h"
 #include "msc_sweep_launch.h"
 #include "msc_fullsym.h"
@@ -254,16 +255,26 @@ class Solver : public SolverBase {
       SweepArgs<T, TM> S = sweep_args(0.0);
       const int64_t chunk = 64;
       int64_t done = 0;
-      if (tune.use_graph && nsteps >= chunk && !timing) {
-        hipGraphExec_t ge = explicit_graph(A, B, (int)chunk);
-        for (; done + chunk <= nsteps; done += chunk) MSC_HIPCK(hipGraphLaunch(ge, st));
+      const bool aa = aa_ok();
+      // AA march: pairs of steps in place on A; an odd count ends with one
+      // two-buffer sweep
+      const int64_t paired = aa ? (nsteps & ~(int64_t)1) : 0;
+      if (tune.use_graph && (aa ? paired : nsteps) >= chunk && !timing) {
+        hipGraphExec_t ge = explicit_graph(A, B, (int)chunk, aa);
+        for (; done + chunk <= (aa ? paired : nsteps); done += chunk) MSC_HIPCK(hipGraphLaunch(ge, st));
       }
+      for (; done < paired; done += 2) {
+        launch_aa(A, false);
+        launch_aa(A, true);
+      }
+      const bool swapped = aa ? (nsteps & 1) : false;
       for (; done < nsteps; ++done) {
-        S.src = (done & 1) ? B : A;
-        S.dst = (done & 1) ? A : B;
+        const int64_t i = aa ? 0 : done;
+        S.src = (i & 1) ? B : A;
+        S.dst = (i & 1) ? A : B;
         launch_sweep_timed(SW_EXPLICIT, S, 1);
       }
-      if (nsteps & 1) std::swap(cur_roles().slot_hist[0], cur_roles().slot_w[0]);
+      if (aa ? swapped : (nsteps & 1)) std::swap(cur_roles().slot_hist[0], cur_roles().slot_w[0]);
       MSC_HIPCK(hipMemcpyAsync(ctl, ctl_h, sizeof(DevCtl), hipMemcpyHostToDevice, st));
       reset_history_from_current();
       // non-finite check on the final state
@@ -274,6 +285,44 @@ class Solver : public SolverBase {
       }
       return MSC_OK;
     });
+  }
+
+  // The in-place (AA) explicit march: periodic boundaries and full-population
+  // storage (FP64, FP32); the cavity and FP16-deviation storage keep the
+  // two-buffer sweep.
+  bool aa_ok() const { return tune.explicit_aa && !walls() && !PopDev<T>::value && G.NS < ((int64_t)1 << 31); }
+
+  // one AA kernel (odd = false: the even kernel) on the population array f
+  void launch_aa(T* f, bool odd) {
+    if constexpr (!PopDev<T>::value) {
+      AaArgs<T> A{};
+      A.f = f;
+      A.N0 = G.N0;
+      A.N1 = G.N1;
+      A.N2 = G.N2;
+      A.lg1 = ilog2(G.N1);
+      A.lg2 = ilog2(G.N2);
+      A.NS = (int)G.NS;
+      A.wp = 1.0 / P.tau_plus;
+      A.wm = 1.0 / P.tau_minus;
+      EvPair ep{};
+      if (timing) {
+        ep = timed_pair(1, 2.0 * Q * (double)G.NS * sizeof(T));
+        A.did_run = run_flags + ep.flag;
+        MSC_HIPCK(hipEventRecord(ep.a, st));
+      }
+      const int grid = (int)((G.NS + 255) / 256);
+      if (odd)
+        hipLaunchKernelGGL((k_aa_odd<L, T>), dim3(grid), dim3(256), 0, st, A);
+      else
+        hipLaunchKernelGGL((k_aa_even<L, T>), dim3(grid), dim3(256), 0, st, A);
+      MSC_HIPCK(hipGetLastError());
+      if (timing) {
+        MSC_HIPCK(hipEventRecord(ep.b, st));
+        ev_live.push_back(ep);
+        if ((int)ev_live.size() >= kFlagCap) collect_timing();
+      }
+    }
   }
 
   // -------------------------------------------------------------- outputs --
@@ -979,6 +1028,7 @@ class Solver : public SolverBase {
   const T* g_b = nullptr;
   int g_chunk = 0;
   float g_sig = 0.0f;
+  bool g_aa = false;
 
   // kernel timing
   bool timing = false;
@@ -1686,20 +1736,30 @@ class Solver : public SolverBase {
     sync();
   }
 
+  // events and run flag of one timed launch (kind 0: dual-time sweep, 1:
+  // explicit march)
+  EvPair timed_pair(int kind, double bytes) {
+    if (!run_flags) {
+      run_flags = keep((int*)dalloc(sizeof(int) * kFlagCap));
+      MSC_HIPCK(hipHostMalloc((void**)&run_flags_h, sizeof(int) * kFlagCap, hipHostMallocDefault));
+      MSC_HIPCK(hipMemsetAsync(run_flags, 0, sizeof(int) * kFlagCap, st));
+    }
+    EvPair ep{};
+    ep.a = get_event();
+    ep.b = get_event();
+    ep.kind = kind;
+    ep.flag = (int)ev_live.size();
+    ep.bytes = bytes;
+    return ep;
+  }
+
   void launch_sweep_timed(int mode, SweepArgs<T, TM> S, int kind) {
     EvPair ep{};
     (void)kind;
     if (timing) {
-      if (!run_flags) {
-        run_flags = keep((int*)dalloc(sizeof(int) * kFlagCap));
-        MSC_HIPCK(hipHostMalloc((void**)&run_flags_h, sizeof(int) * kFlagCap, hipHostMallocDefault));
-        MSC_HIPCK(hipMemsetAsync(run_flags, 0, sizeof(int) * kFlagCap, st));
-      }
-      ep.a = get_event();
-      ep.b = get_event();
-      ep.kind = (mode == SW_EXPLICIT) ? 1 : 0;
-      ep.flag = (int)ev_live.size();
-      ep.bytes = sweep_bytes(mode, S.order, S.q) + ((mode == SW_DTS_SETUP && S.recon) ? (double)(D + 1) * G.NS * 8.0 : 0.0);
+      ep = timed_pair((mode == SW_EXPLICIT) ? 1 : 0,
+                      sweep_bytes(mode, S.order, S.q) +
+                          ((mode == SW_DTS_SETUP && S.recon) ? (double)(D + 1) * G.NS * 8.0 : 0.0));
       S.did_run = run_flags + ep.flag;
     }
     if (mode == SW_DTS_SETUP) {
@@ -1717,8 +1777,8 @@ class Solver : public SolverBase {
     }
   }
 
-  hipGraphExec_t explicit_graph(T* A, T* B, int chunk) {
-    if (gexec && g_a == A && g_b == B && g_chunk == chunk && g_sig == sig) return gexec;
+  hipGraphExec_t explicit_graph(T* A, T* B, int chunk, bool aa) {
+    if (gexec && g_a == A && g_b == B && g_chunk == chunk && g_sig == sig && g_aa == aa) return gexec;
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     gexec = nullptr;
@@ -1727,6 +1787,10 @@ class Solver : public SolverBase {
     MSC_HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     SweepArgs<T, TM> S = sweep_args(0.0);
     for (int i = 0; i < chunk; ++i) {
+      if (aa) {
+        launch_aa(A, (i & 1) != 0);
+        continue;
+      }
       S.src = (i & 1) ? B : A;
       S.dst = (i & 1) ? A : B;
       if (D == 2)
@@ -1740,6 +1804,7 @@ class Solver : public SolverBase {
     g_b = B;
     g_chunk = chunk;
     g_sig = sig;
+    g_aa = aa;
     return gexec;
   }
 

@@ -356,6 +356,11 @@ template <class L, class T, class TM, int MODE>
 __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const RawSite<L, T, TM, MODE>& r,
                                             typename CompT<T>::type* f, typename CompT<T>::type* C,
                                             double* hout, double* Mtrial = nullptr, double* mnout = nullptr) {
+  // Multiply-adds are fused only within one expression, as written here, not
+  // by the optimiser across statements: every kernel that inlines the
+  // collision (the tiled sweep, the in-place march) then rounds it the same
+  // way and their results agree bit for bit.
+#pragma clang fp contract(on)
   using CT = typename CompT<T>::type;
   constexpr int Q = L::Q, D = L::D;
   constexpr bool DV = PopDev<T>::value;
