@@ -95,7 +95,7 @@ msc_status run(const int* n, double tau_plus, double tau_minus, const T* f, cons
   const int64_t NS = (int64_t)N0 * N1 * N2;
   const int tile_id = auto_sweep_tile<L>(N1, N2);
   const TileCfg tile = TileSet<L>::get(tile_id);
-  const int strip = sweep_strip_for<L, T>(tile, N0, N1, N2, 0);
+  const int strip = sweep_strip_for<L, T>(tile, N0, N1, N2, 0, STRIP_DUAL);
   const int64_t grid = (int64_t)(N1 / tile.T1) * (N2 / tile.T2) * (N0 / strip);
   if (grid > kScratchDoubles) return MSC_ERR_INVALID_ARG;
   double* parts = nullptr;

@@ -1617,7 +1617,8 @@ class Solver : public SolverBase {
 
   // ------------------------------------------------------ sweep config --
   int tile_id = 0, strip_L = 1;
-  int strip_setup = 1;  // planes per strip of the first sweep of a step
+  int strip_setup = 1;     // planes per strip of the first sweep of a step
+  int strip_explicit = 1;  // planes per strip of the tiled explicit sweep
   TileCfg tile{};
   // 2D with the shadow corrector and tiles spanning whole rows: the sweep
   // also does the forward row transform of P r
@@ -1642,18 +1643,23 @@ class Solver : public SolverBase {
     if (best < 0) best = auto_sweep_tile<L>(G.N1, G.N2);
     tile_id = best;
     tile = TileSet<L>::get(best);
-    strip_L = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip);
-    strip_setup = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, true);
+    strip_L = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_DUAL);
+    strip_setup = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_SETUP);
+    strip_explicit = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_EXPLICIT);
     fuse_rows = D == 2 && P.corrector == MSC_CORRECTOR_SHADOW && tile.T1 == 1 && tile.T2 == G.N2 &&
                 tile.NT == tile.T2 && corrector_supported() && tune.fuse_rows != 0;
     fuse_inv = fuse_rows && strip_L == 1 && tune.fuse_rows >= 2;
   }
 
-  int sweep_grid(int mode = SW_DTS) const {
-    const int Ls = (mode == SW_DTS_SETUP) ? strip_setup : strip_L;
-    return (int)((int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2) * (G.N0 / Ls));
+  int strip_of(int mode) const {
+    return (mode == SW_DTS_SETUP) ? strip_setup : (mode == SW_EXPLICIT ? strip_explicit : strip_L);
   }
-  int sweep_grid_max() const { return std::max(sweep_grid(), sweep_grid(SW_DTS_SETUP)); }
+  int sweep_grid(int mode = SW_DTS) const {
+    return (int)((int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2) * (G.N0 / strip_of(mode)));
+  }
+  int sweep_grid_max() const {
+    return std::max({sweep_grid(), sweep_grid(SW_DTS_SETUP), sweep_grid(SW_EXPLICIT)});
+  }
 
   SweepArgs<T, TM> sweep_args(double a) {
     SweepArgs<T, TM> S{};
@@ -1762,10 +1768,8 @@ class Solver : public SolverBase {
                           ((mode == SW_DTS_SETUP && S.recon) ? (double)(D + 1) * G.NS * 8.0 : 0.0));
       S.did_run = run_flags + ep.flag;
     }
-    if (mode == SW_DTS_SETUP) {
-      S.L = strip_setup;
-      S.nstrip = G.N0 / strip_setup;
-    }
+    S.L = strip_of(mode);
+    S.nstrip = G.N0 / S.L;
     if (D == 2)
       launch_sweep_d2<T, TM>(tile_id, mode, S, sweep_grid(mode), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
     else
@@ -1786,6 +1790,8 @@ class Solver : public SolverBase {
     sync();
     MSC_HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     SweepArgs<T, TM> S = sweep_args(0.0);
+    S.L = strip_explicit;
+    S.nstrip = G.N0 / strip_explicit;
     for (int i = 0; i < chunk; ++i) {
       if (aa) {
         launch_aa(A, (i & 1) != 0);
@@ -1794,9 +1800,9 @@ class Solver : public SolverBase {
       S.src = (i & 1) ? B : A;
       S.dst = (i & 1) ? A : B;
       if (D == 2)
-        launch_sweep_d2<T, TM>(tile_id, SW_EXPLICIT, S, sweep_grid(), st);
+        launch_sweep_d2<T, TM>(tile_id, SW_EXPLICIT, S, sweep_grid(SW_EXPLICIT), st);
       else
-        launch_sweep_d3<T, TM>(tile_id, SW_EXPLICIT, S, sweep_grid(), st);
+        launch_sweep_d3<T, TM>(tile_id, SW_EXPLICIT, S, sweep_grid(SW_EXPLICIT), st);
     }
     MSC_HIPCK(hipStreamEndCapture(st, &graph));
     MSC_HIPCK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));

@@ -131,25 +131,39 @@ int auto_sweep_tile(int N1, int N2) {
 }
 
 // Strip length: the requested one, or the longest strip (at most 64 planes in
-// 2D, 32 in 3D) that keeps >= 1024 blocks (2D) or >= 512 (3D, more work per
-// site): short strips cut the per-block chain of plane steps, which bounds
-// small grids; long ones cut the two halo planes per strip.  Measured optimum
-// of the sweep at N = 256 ... 4096 (2D) and N = 64 ... 256 (3D; with FP64
-// populations, two blocks per CU with the two-barrier rings, 512 blocks
-// against 256: N = 128 march 1%, explicit sweep 10% faster).  Always a divisor
-// of N0.
+// 2D, 32 in 3D) that keeps a target block count: short strips cut the
+// per-block chain of plane steps, which bounds small grids; long ones cut the
+// two halo planes per strip.  Always a divisor of N0.  Targets by kind:
 //
-// setup: the first sweep of a step.  With FP64 D3Q19 populations it holds
-// three history states and runs one block per CU; one wave of 256 blocks then
-// keeps every tile of a strip resident on its XCD, so the halo rows a block
-// re-collides are its neighbours' rows in that XCD's L2 (the setup sweep read
-// 2.0x its algorithmic bytes with 512 blocks).
+// STRIP_EXPLICIT (the tiled explicit sweep): >= 1024 blocks (2D) or 512 (3D,
+// more work per site), the measured optimum at N = 256 ... 4096 (2D) and
+// N = 64 ... 256 (3D; with FP64 populations, two blocks per CU with the
+// two-barrier rings, 512 blocks against 256: explicit sweep 10% faster).
+//
+// STRIP_DUAL (the dual-time sweeps after the first of a step): >= 512 blocks
+// in 2D, strips twice as long as the explicit sweep's, whose extra halo planes
+// weigh more there (each re-collided site also re-reads the history term and
+// the correction): 2D corrected march N = 512 FP32 95 -> 84 us per step,
+// N = 1024 FP32 191 -> 182 us, FP64 387 -> 333 us (N = 256 and 2048
+// unchanged); 3D as the explicit sweep.
+//
+// STRIP_SETUP (the first sweep of a step): as STRIP_DUAL, except that with FP64
+// D3Q19 populations it holds three history states and runs one block per CU;
+// one wave of 256 blocks then keeps every tile of a strip resident on its XCD,
+// so the halo rows a block re-collides are its neighbours' rows in that XCD's
+// L2 (the setup sweep read 2.0x its algorithmic bytes with 512 blocks).
+enum StripKind { STRIP_EXPLICIT = 0, STRIP_DUAL = 1, STRIP_SETUP = 2 };
+
 template <class L, class T>
-int sweep_strip_for(const TileCfg& tile, int N0, int N1, int N2, int requested, bool setup = false) {
+int sweep_strip_for(const TileCfg& tile, int N0, int N1, int N2, int requested, StripKind kind) {
   const int64_t tiles = (int64_t)(N1 / tile.T1) * (N2 / tile.T2);
   int Lp = requested;
   if (Lp <= 0) {
-    const int64_t target = (L::D == 2) ? 1024 : ((setup && sizeof(T) == 8) ? 256 : 512);
+    int64_t target;
+    if (L::D == 2)
+      target = (kind == STRIP_EXPLICIT) ? 1024 : 512;
+    else
+      target = (kind == STRIP_SETUP && sizeof(T) == 8) ? 256 : 512;
     const int Lmax = (L::D == 2) ? 64 : 32;
     Lp = 1;
     while (Lp < Lmax && tiles * (N0 / (Lp * 2)) >= target) Lp *= 2;
