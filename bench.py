@@ -251,6 +251,109 @@ def extra_workload(msc, W, stream, torch, name, storage, extrap=2, ref_cache=Non
     }
 
 
+def re_sweep(msc, W, stream, torch, res=(1e-4, 1e-2, 1.0, 10.0, 100.0), storages=("fp32", "fp16dev"),
+             S_ladder=(64, 128, 256, 512), eps_rel=(1e-6, 1e-7, 1e-8)):
+    """Reynolds sweep of the D2Q9 N = 1024 random-field workload (seeded
+    |k|^-3 spectrum, |k| <= 16, nu = 1/6, Re set by U, horizon 0.1 N^2/nu).
+    Per Re: the FP64 explicit endpoint as the reference; per storage the
+    explicit march (timed over the whole horizon) and the corrected march
+    over a ladder of physical step counts S (fewest first) and tolerances
+    eps = e Re (the residual scales with U; e from eps_rel, loosest first):
+    every candidate runs the whole horizon, and the fastest one passing the
+    1% gate (RMS velocity difference from the FP64 explicit endpoint over its
+    RMS) is reported with its speedup over the same-storage explicit march;
+    the Stokes-decay error (the matched gate's reference, valid for the
+    linear regime Re <= 1) is reported beside it.  The sweep kernel's
+    achieved bandwidth comes from per-launch events over the first steps of
+    the chosen candidate."""
+    base = W.config("rand2d_n1024_fp32")
+    N, nu, d = base["N"], base["nu"], 2
+    T_end = base["T_end"]
+    tnu = N * N / nu
+    out = []
+    for Re in res:
+        U = Re * nu / N
+        cfg = dict(base, Re=Re, U=U)
+        p0, u0 = W.initial_fields(cfg)
+        u_st = stokes_decay(u0, float(T_end), nu)
+
+        def mk(st, corrector, S=64, eps=1e-8):
+            p = msc.make_params(d, N, dt=T_end / S, eps=eps, storage=st, corrector=corrector, n_min=base["nmin"],
+                                extrap_states=2)
+            return msc.Solver(p, p0, u0, stream=stream)
+
+        r = mk("fp64", "picard")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.explicit_step(int(T_end))
+        torch.cuda.synchronize()
+        t_ref = time.perf_counter() - t0
+        u_ref = r.moments()[1:]
+        r.close()
+        nref = max(rms(u_ref), 1e-300)
+        row = {"Re": Re, "U": U, "fp64_explicit_s": t_ref, "fp64_explicit_abs_vs_stokes": rms(u_ref - u_st),
+               "storages": {}}
+        for st in storages:
+            e = mk(st, "picard")
+            e.explicit_step(64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e.explicit_step(int(T_end) - 64)
+            torch.cuda.synchronize()
+            t_exp = (time.perf_counter() - t0) * T_end / (T_end - 64)
+            u_exp = e.moments()[1:]
+            e.close()
+            e_exp = rms(u_exp - u_ref) / nref
+            cands = []
+            best = None
+            for S in S_ladder:
+                for er in eps_rel:
+                    eps = er * Re
+                    s = mk(st, "shadow", S, eps)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    rc, stats = s.bdf2_step(S, raise_on_fail=False)
+                    torch.cuda.synchronize()
+                    t_msc = time.perf_counter() - t0
+                    done = sum(1 for x in stats if x["converged"])
+                    u_msc = s.moments()[1:] if rc == 0 else None
+                    s.close()
+                    e_msc = rms(u_msc - u_ref) / nref if u_msc is not None else None
+                    ok = rc == 0 and e_msc is not None and e_msc <= 1e-2
+                    c = {"S": S, "eps": eps, "status": int(rc), "steps_accepted": done, "s": t_msc,
+                         "mean_inner": float(np.mean([x["iters"] for x in stats[:max(done, 1)]])) if stats else None,
+                         "rel_vs_fp64_explicit": e_msc,
+                         "abs_vs_stokes": rms(u_msc - u_st) if u_msc is not None else None, "gate_1pct": ok}
+                    cands.append(c)
+                    if ok and (best is None or t_msc < best["s"]):
+                        best = c
+                if best is not None:
+                    break
+            res_st = {"explicit_s": t_exp, "explicit_rel_vs_fp64_explicit": e_exp,
+                      "explicit_wall_s_per_viscous_time": t_exp * tnu / T_end, "candidates": cands, "best": best,
+                      "speedup_vs_explicit": (t_exp / best["s"]) if best else None,
+                      "speedup_gate": "1%" if best else None}
+            if best is not None:
+                s = mk(st, "shadow", best["S"], best["eps"])
+                s.set_kernel_timing(True)
+                s.bdf2_step(min(best["S"], 16), raise_on_fail=False)
+                ks, kn, kb = s.kernel_time(0)
+                s.close()
+                res_st["msc_wall_s_per_viscous_time"] = best["s"] * tnu / T_end
+                res_st["msc_not_less_accurate_than_explicit"] = best["rel_vs_fp64_explicit"] <= e_exp
+                res_st["sweep"] = {"avg_launch_us": ks / max(kn, 1) * 1e6, "bytes_per_launch": kb,
+                                   "achieved_GBs": kb / (ks / kn) / 1e9 if kn else None,
+                                   "frac": kb / (ks / kn) / 1e9 / HBM_PEAK_GBS if kn else None}
+            row["storages"][st] = res_st
+            log(f"[re-sweep] Re={Re:g} {st}: explicit {t_exp:.2f} s (e {e_exp:.2e}); best "
+                + (f"S={best['S']} eps={best['eps']:.1e} {best['s']:.3f} s e {best['rel_vs_fp64_explicit']:.2e} "
+                   f"speedup {t_exp / best['s']:.1f}" if best else "none passed"))
+        out.append(row)
+    return {"workload": "rand2d_n1024 (D2Q9 N=1024, seeded |k|^-3 field, |k| <= 16, nu=1/6)",
+            "horizon_lattice_steps": T_end, "gate": "1% (RMS velocity difference from the FP64 explicit endpoint "
+            "over its RMS)", "rows": out}
+
+
 def adjoint_workload(msc, W, stream, torch):
     """Differentiable march of the vorticity-control workload (D2Q9 N=256,
     20 steps of dt=64, FP32): forward march, forward with per-step
@@ -742,6 +845,9 @@ def main():
                     help="skip the other workloads (FP32 3D, 2D N=256 and N=1024, adjoint, 2D matched-gate cells)")
     ap.add_argument("--march-only", action="store_true",
                     help="only the timed corrected march and its sweep timing pass (counter runs)")
+    ap.add_argument("--re-sweep", action="store_true",
+                    help="only the D2Q9 N=1024 Reynolds sweep (FP32 and FP16-deviation storage, 1%% gate)")
+    ap.add_argument("--re-list", default="", help="Reynolds numbers of --re-sweep, comma separated")
     ap.add_argument("--envelope", action="store_true",
                     help="only the operating-envelope measurements (rho_obs along Lambda and nu, (Re, dt) cells)")
     ap.add_argument("--cavity", action="store_true",
@@ -780,6 +886,12 @@ def main():
         return
     if args.envelope:
         print(json.dumps({"envelope": envelope(msc, W, stream, torch)}), flush=True)
+        return
+    if args.re_sweep:
+        kw = {}
+        if args.re_list:
+            kw["res"] = tuple(float(v) for v in args.re_list.split(","))
+        print(json.dumps({"re_sweep": re_sweep(msc, W, stream, torch, **kw)}), flush=True)
         return
     if args.fullsym:
         print(json.dumps({"full_symbol": fullsym_cost(msc, W, stream, torch)}), flush=True)

@@ -99,7 +99,8 @@ typedef enum msc_wall_operator {
 typedef enum msc_storage {
   MSC_STORAGE_FP64 = 0, /* FP64 populations, FP64 arithmetic */
   MSC_STORAGE_FP32 = 1, /* FP32 populations and arithmetic; FP64 BDF history
-                           combination, residual reductions and per-wavevector solve */
+                           combination, collision temporaries, residual reductions and
+                           per-wavevector solve */
   MSC_STORAGE_FP16_DEV = 2 /* populations as g = (f - feq(P f))/sigma in FP16 plus P f in
                               FP32, sigma a power of two chosen from the data when a state
                               is set (msc_init, msc_set_populations, msc_set_state); FP32

@@ -450,14 +450,19 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
       f[k] += (CT)L::w(k) * (d0 + (CT)3 * cu);
     }
   }
-  // Collision arithmetic type: FP64 temporaries in the dual-time modes of
-  // every storage type.  The inner fixed point amplifies the rounding of the
-  // collision's conserved moments by about dt (the slow hydrodynamic modes of
-  // I - J have eigenvalues near a_q), so FP32 arithmetic there would put an
-  // error of ~eps32 dt sqrt(S) on the velocity; the populations, the trial
-  // and the residual stay in the storage's compute type.  The explicit map
-  // has no such amplification and keeps the compute type.
-  using KT = typename std::conditional<MODE == SW_EXPLICIT, CT, double>::type;
+  // Collision arithmetic type: FP64 temporaries in every mode and storage
+  // type; the populations, the trial and the residual stay in the storage's
+  // compute type.  In the dual-time modes the inner fixed point amplifies the
+  // rounding of the collision's conserved moments by about dt (the slow
+  // hydrodynamic modes of I - J have eigenvalues near a_q): FP32 arithmetic
+  // there would put an error of ~eps32 dt sqrt(S) on the velocity.  In the
+  // explicit map the FP32 weights (1/9, 1/36 and 1/18, 1/36 are not binary
+  // fractions) make the equilibrium's mass and momentum differ from the
+  // moments it is built from by a fixed relative ~1e-8 of one sign, so each
+  // step scales them by 1 + O(1e-8) and the drift grows linearly with the
+  // step count (a 2% velocity error after the 6.3e5 steps of 0.1 N^2/nu at
+  // N = 1024).
+  using KT = double;
   KT M[4] = {0, 0, 0, 0};
   if constexpr (DV) {
     // deviation storage keeps P f itself: combine the stored FP32 moments
