@@ -32,12 +32,26 @@ namespace msc {
 // trial; the same with the previous correction's lift fused into the load;
 // and the first sweep of a physical step, which also forms the BDF history
 // term h_q (Eq. bdf2) and the extrapolated trial (Sec. 3.1) while loading.
-enum { SW_EXPLICIT = 0, SW_DTS = 1, SW_DTS_LIFT = 2, SW_DTS_SETUP = 3, SW_DTS_LIFT_ROWS = 4 };
+enum { SW_EXPLICIT = 0, SW_DTS = 1, SW_DTS_LIFT = 2, SW_DTS_SETUP = 3, SW_DTS_LIFT_ROWS = 4, SW_DTS_SETUP1 = 5 };
 // SW_DTS_LIFT_ROWS: the lift mode with the correction's inverse row transform
 // done by the sweep itself (2D, tiles spanning whole rows, one-plane strips):
 // each block inverts the band spectrum rows of its source planes in LDS
 // instead of reading dm.
 __host__ __device__ constexpr bool lift_mode(int m) { return m == SW_DTS_LIFT || m == SW_DTS_LIFT_ROWS; }
+// SW_DTS_SETUP1: the first sweep of a step with a trial extrapolated from at
+// most two states (order <= 1), which holds no f^{n-2} registers
+__host__ __device__ constexpr bool setup_mode(int m) { return m == SW_DTS_SETUP || m == SW_DTS_SETUP1; }
+// first sweep whose halo loads are issued a plane ahead (see k_sweep)
+template <class L, class T, int MODE>
+__host__ __device__ constexpr bool setup_halo_prefetch() {
+  return MODE == SW_DTS_SETUP1 && L::D == 3 && sizeof(T) == 8;
+}
+// halo ring sites of a T1 x T2 tile (one ring along each axis the tile does
+// not span)
+__host__ __device__ inline int tile_halo_sites(int T1, int T2, int N1, int N2) {
+  const int h1 = (T1 < N1) ? 1 : 0, h2 = (T2 < N2) ? 1 : 0;
+  return 2 * h1 * (T2 + 2 * h2) + 2 * h2 * T1;
+}
 
 template <class T>
 struct CompT;
@@ -291,14 +305,14 @@ struct RawSite {
   static constexpr int Q = L::Q, D1 = L::D + 1;
   static constexpr bool DV = PopDev<T>::value;
   T f0[Q];
-  T f1[MODE == SW_DTS_SETUP ? Q : 1];
+  T f1[setup_mode(MODE) ? Q : 1];
   T f2[MODE == SW_DTS_SETUP ? Q : 1];
   float M0[DV ? D1 : 1];  // stored moments of each deviation buffer
-  float M1[DV && MODE == SW_DTS_SETUP ? D1 : 1];
+  float M1[DV && setup_mode(MODE) ? D1 : 1];
   float M2[DV && MODE == SW_DTS_SETUP ? D1 : 1];
   TM dmv[lift_mode(MODE) ? D1 : 1];
   double hv[MODE == SW_EXPLICIT ? 1 : D1];  // h, or m^n in setup mode
-  double mpv[MODE == SW_DTS_SETUP ? D1 : 1];
+  double mpv[setup_mode(MODE) ? D1 : 1];
 };
 
 template <class L, class T, class TM, int MODE>
@@ -313,21 +327,23 @@ __device__ __forceinline__ void load_raw(const SweepArgs<T, TM>& A, const SrcPtr
 #pragma unroll
     for (int b = 0; b <= D; ++b) r.M0[b] = dev_moments(P.s0, Q, NS)[b * NS + site];
   }
-  if (MODE == SW_DTS_SETUP) {
+  if constexpr (setup_mode(MODE)) {
     if (A.order >= 1) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) r.f1[k] = P.s1[k * NS + site];
-      if constexpr (DV && MODE == SW_DTS_SETUP) {
+      if constexpr (DV) {
 #pragma unroll
         for (int b = 0; b <= D; ++b) r.M1[b] = dev_moments(P.s1, Q, NS)[b * NS + site];
       }
     }
-    if (A.order >= 2) {
+    if constexpr (MODE == SW_DTS_SETUP) {
+      if (A.order >= 2) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) r.f2[k] = P.s2[k * NS + site];
-      if constexpr (DV && MODE == SW_DTS_SETUP) {
+        for (int k = 0; k < Q; ++k) r.f2[k] = P.s2[k * NS + site];
+        if constexpr (DV) {
 #pragma unroll
-        for (int b = 0; b <= D; ++b) r.M2[b] = dev_moments(P.s2, Q, NS)[b * NS + site];
+          for (int b = 0; b <= D; ++b) r.M2[b] = dev_moments(P.s2, Q, NS)[b * NS + site];
+        }
       }
     }
 #pragma unroll
@@ -365,7 +381,7 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
   constexpr int Q = L::Q, D = L::D;
   constexpr bool DV = PopDev<T>::value;
   double h[4] = {0, 0, 0, 0};
-  if (MODE == SW_DTS_SETUP) {
+  if constexpr (setup_mode(MODE)) {
     // m^n: loaded, or with recon formed here from f^n and the previous step's
     // history term (Eq. macro-reconstruct, the reconstruction the previous
     // step's acceptance left to this sweep)
@@ -404,26 +420,30 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
     for (int b = 0; b <= D; ++b)
       h[b] = (A.q == 1) ? mn[b] / A.dt : (4.0 * mn[b] - r.mpv[b]) / (2.0 * A.dt);
     if constexpr (DV) {
-      CT g1[Q], g2[Q];
+      CT g1[Q], g2[MODE == SW_DTS_SETUP ? Q : 1];
       dev_rebuild<L>(r.f0, r.M0, A.sig, f);
       if (A.order >= 1) dev_rebuild<L>(r.f1, r.M1, A.sig, g1);
-      if (A.order >= 2) dev_rebuild<L>(r.f2, r.M2, A.sig, g2);
+      if constexpr (MODE == SW_DTS_SETUP) {
+        if (A.order >= 2) dev_rebuild<L>(r.f2, r.M2, A.sig, g2);
+      }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        if (A.order == 1)
+        if (A.order == 1) {
           f[k] = (CT)2 * f[k] - g1[k];
-        else if (A.order >= 2)
-          f[k] = (CT)3 * f[k] - (CT)3 * g1[k] + g2[k];
+        } else if constexpr (MODE == SW_DTS_SETUP) {
+          if (A.order >= 2) f[k] = (CT)3 * f[k] - (CT)3 * g1[k] + g2[k];
+        }
       }
     } else {
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        if (A.order == 0)
+        if (A.order == 0) {
           f[k] = (CT)r.f0[k];
-        else if (A.order == 1)
+        } else if (A.order == 1) {
           f[k] = (CT)2 * (CT)r.f0[k] - (CT)r.f1[k];
-        else
+        } else if constexpr (MODE == SW_DTS_SETUP) {
           f[k] = (CT)3 * (CT)r.f0[k] - (CT)3 * (CT)r.f1[k] + (CT)r.f2[k];
+        }
       }
     }
 #pragma unroll
@@ -473,6 +493,8 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
         M[b] = (A.order == 0) ? (KT)r.M0[b]
                               : (A.order == 1 ? (KT)2 * (KT)r.M0[b] - (KT)r.M1[b]
                                               : (KT)3 * (KT)r.M0[b] - (KT)3 * (KT)r.M1[b] + (KT)r.M2[b]);
+      else if constexpr (MODE == SW_DTS_SETUP1)
+        M[b] = (A.order == 0) ? (KT)r.M0[b] : (KT)2 * (KT)r.M0[b] - (KT)r.M1[b];
       else
         M[b] = (KT)r.M0[b];
       if constexpr (lift_mode(MODE)) M[b] += (KT)r.dmv[b];
@@ -573,9 +595,9 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
 // three above the 128 that allow four waves per SIMD; bounded to four.
 template <class L, class T, int MODE, int T1>
 __host__ __device__ constexpr int sweep_min_waves() {
-  return (L::D == 2 && sizeof(T) == 8 && MODE == SW_DTS_SETUP)                          ? 2
+  return (L::D == 2 && sizeof(T) == 8 && setup_mode(MODE))                              ? 2
          : (L::D == 2 && sizeof(T) == 4 && (MODE == SW_DTS || MODE == SW_DTS_LIFT)) ? 4
-         : (sweep_two_barriers<L, T>() && MODE != SW_DTS_SETUP && T1 > 1)             ? 2
+         : (sweep_two_barriers<L, T>() && !setup_mode(MODE) && T1 > 1)                 ? 2
                                                                                        : 1;
 }
 
@@ -613,7 +635,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
     const uint64_t ph = A.ctl->phase;
     if (!phase_ready(ph, A.n, A.ell)) return;  // uniform for the grid
     const Roles& ro = A.ctl->roles[A.n & 1];
-    if (MODE == SW_DTS_SETUP) {
+    if (setup_mode(MODE)) {
       P.s0 = A.fb.p[ro.slot_hist[0]];
       P.s1 = A.fb.p[ro.slot_hist[1]];
       P.s2 = A.fb.p[ro.slot_hist[2]];
@@ -674,6 +696,22 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
       load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs0 * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
     }
   }
+  // The D3Q19 FP64 first sweep runs one wave per SIMD (history states and
+  // the collision in flight), so nothing would hide the latency of its halo
+  // loads: they are issued one plane ahead like the owned ones.  The launcher
+  // takes this instantiation only when every thread has at most one halo
+  // site (setup_halo_prefetch).
+  constexpr bool HPF = setup_halo_prefetch<L, T, MODE>();
+  const bool hown = HPF && tid < nhalo;
+  int hi1 = 0, hi2 = 0;
+  RawSite<L, T, TM, MODE> hraw;
+  if constexpr (HPF) {
+    if (hown) {
+      halo_at(tid, hi1, hi2);
+      const int xs0 = wrapi(x0 - 1, N0);
+      load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs0 * N1 + wrapi(b1 + hi1, N1)) * N2 + wrapi(b2 + hi2, N2), hraw);
+    }
+  }
   // SW_DTS_LIFT_ROWS: inverse transform along y of the band spectrum rows of
   // the source planes x0-1, x0, x0+1 (Eq. fft-convention, the 1/N_Omega is in
   // the spectrum): the conjugate-symmetric extension of each field's half
@@ -732,21 +770,36 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
     for (int j = 0; j < SPT; ++j) {
       const int s = tid + j * NT;
       const int i1 = s / T2, i2 = s - (s / T2) * T2;
-      RawSite<L, T, TM, MODE> cur = raw[j];
-      if (it + 1 < A.L + 2) {
-        const int xn = wrapi(x0 + it, N0);
-        load_raw<L, T, TM, MODE>(A, P, ((int64_t)xn * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
-        if constexpr (ROWINV) {
-          const cpx<CT>* row = dmr + 2 * (it + 1) * T2;
-          raw[j].dmv[0] = (TM)row[i2].x;
-          raw[j].dmv[1] = (TM)row[i2].y;
-          raw[j].dmv[2] = (TM)row[T2 + i2].x;
+      // next plane's loads: issued before this plane's collision (a full
+      // plane step to land), or with the halo prefetch after it (the
+      // registers of this plane's loads are free again; half a plane step)
+      RawSite<L, T, TM, MODE> cur;
+      auto load_next = [&](RawSite<L, T, TM, MODE>& dstr) {
+        if (it + 1 < A.L + 2) {
+          const int xn = wrapi(x0 + it, N0);
+          load_raw<L, T, TM, MODE>(A, P, ((int64_t)xn * N1 + (b1 + i1)) * N2 + (b2 + i2), dstr);
+          if constexpr (ROWINV) {
+            const cpx<CT>* row = dmr + 2 * (it + 1) * T2;
+            dstr.dmv[0] = (TM)row[i2].x;
+            dstr.dmv[1] = (TM)row[i2].y;
+            dstr.dmv[2] = (TM)row[T2 + i2].x;
+          }
         }
-      }
+      };
       CT C[Q];
       double hs[4], mns[4];
-      collide_raw<L, T, TM, MODE>(A, cur, fcur[j], C, hs, mcur[j], mns);
-      if (MODE == SW_DTS_SETUP && it >= 1 && it <= A.L) {
+      if constexpr (HPF) {
+        collide_raw<L, T, TM, MODE>(A, raw[j], fcur[j], C, hs, mcur[j], mns);
+        // keep the next plane's loads below the collision that frees their
+        // registers (the scheduler would otherwise hoist them)
+        __builtin_amdgcn_sched_barrier(0);
+        load_next(raw[j]);
+      } else {
+        cur = raw[j];
+        load_next(raw[j]);
+        collide_raw<L, T, TM, MODE>(A, cur, fcur[j], C, hs, mcur[j], mns);
+      }
+      if (setup_mode(MODE) && it >= 1 && it <= A.L) {
         const int64_t site = ((int64_t)xs * N1 + (b1 + i1)) * N2 + (b2 + i2);
 #pragma unroll
         for (int bb = 0; bb <= D; ++bb) A.h[bb * NS + site] = hs[bb];
@@ -778,15 +831,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
       cmxc[j] = C[KMX];
     }
     // ---- halo ring sources (only along axes the tile does not span) -------
-    for (int t = tid; t < nhalo; t += NT) {
-      int i1, i2;
-      halo_at(t, i1, i2);
-      const int p1 = wrapi(b1 + i1, N1), p2 = wrapi(b2 + i2, N2);
-      RawSite<L, T, TM, MODE> hr;
-      load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs * N1 + p1) * N2 + p2, hr);
-      CT f[Q], C[Q];
-      double hs[4];
-      collide_raw<L, T, TM, MODE>(A, hr, f, C, hs);
+    auto push_halo = [&](int i1, int i2, const CT* C) {
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         if (is_local<L>(k)) continue;
@@ -804,6 +849,31 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
         } else {
           if (wM) ldsM[sM][gi][di] = (LT)C[k];
         }
+      }
+    };
+    if constexpr (HPF) {
+      if (hown) {
+        CT f[Q], C[Q];
+        double hs[4];
+        collide_raw<L, T, TM, MODE>(A, hraw, f, C, hs);
+        __builtin_amdgcn_sched_barrier(0);
+        if (it + 1 < A.L + 2) {
+          const int xn = wrapi(x0 + it, N0);
+          load_raw<L, T, TM, MODE>(A, P, ((int64_t)xn * N1 + wrapi(b1 + hi1, N1)) * N2 + wrapi(b2 + hi2, N2), hraw);
+        }
+        push_halo(hi1, hi2, C);
+      }
+    } else {
+      for (int t = tid; t < nhalo; t += NT) {
+        int i1, i2;
+        halo_at(t, i1, i2);
+        const int p1 = wrapi(b1 + i1, N1), p2 = wrapi(b2 + i2, N2);
+        RawSite<L, T, TM, MODE> hr;
+        load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs * N1 + p1) * N2 + p2, hr);
+        CT f[Q], C[Q];
+        double hs[4];
+        collide_raw<L, T, TM, MODE>(A, hr, f, C, hs);
+        push_halo(i1, i2, C);
       }
     }
     __syncthreads();

@@ -60,6 +60,9 @@ void launch_sweep_tile(int mode, const SweepArgs<T, TM>& A, int grid, hipStream_
     launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS>(A, grid, st, ev0, ev1);
   else if (mode == SW_DTS_LIFT)
     launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_LIFT>(A, grid, st, ev0, ev1);
+  else if (mode == SW_DTS_SETUP && A.order <= 1 &&
+           (!setup_halo_prefetch<L, T, SW_DTS_SETUP1>() || tile_halo_sites(T1, T2, A.N1, A.N2) <= NT))
+    launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_SETUP1>(A, grid, st, ev0, ev1);
   else if (mode == SW_DTS_SETUP)
     launch_sweep_mode<L, T, TM, NT, T1, T2, SW_DTS_SETUP>(A, grid, st, ev0, ev1);
   else if constexpr (T1 == 1 && NT == T2 && L::D == 2)
