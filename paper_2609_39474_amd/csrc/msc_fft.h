@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A, Accep
 // Schur solve on the band |j_x| <= N_x/4 (zero elsewhere), and the inverse
 // transform along x, in place in the band spectrum array.
 template <class L, class T, class CT, class TM>
-__global__ __launch_bounds__(256) void k_fft2_cols_solve(Fft2Args<CT, TM> A, AcceptArgs<L, T> Ac, FinishArgs Fin) {
+__global__ __launch_bounds__(512) void k_fft2_cols_solve(Fft2Args<CT, TM> A, AcceptArgs<L, T> Ac, FinishArgs Fin) {
   if (A.decide) {
     // Algorithm 1 with the row pass fused into the sweep: decide here; if
     // accepted, reconstruct m^{n+1} over the whole field instead
