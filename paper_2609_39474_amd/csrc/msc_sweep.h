@@ -44,7 +44,7 @@ __host__ __device__ constexpr bool setup_mode(int m) { return m == SW_DTS_SETUP 
 // first sweep whose halo loads are issued a plane ahead (see k_sweep)
 template <class L, class T, int MODE>
 __host__ __device__ constexpr bool setup_halo_prefetch() {
-  return MODE == SW_DTS_SETUP1 && L::D == 3 && sizeof(T) == 8;
+  return MODE == SW_DTS_SETUP1 && L::D == 3;
 }
 // halo ring sites of a T1 x T2 tile (one ring along each axis the tile does
 // not span)
@@ -696,11 +696,11 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
       load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs0 * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
     }
   }
-  // The D3Q19 FP64 first sweep runs one wave per SIMD (history states and
-  // the collision in flight), so nothing would hide the latency of its halo
-  // loads: they are issued one plane ahead like the owned ones.  The launcher
-  // takes this instantiation only when every thread has at most one halo
-  // site (setup_halo_prefetch).
+  // The D3Q19 first sweep runs one wave per SIMD in every storage type
+  // (history states and the FP64 collision in flight), so nothing would hide
+  // the latency of its halo loads: they are issued one plane ahead like the
+  // owned ones.  The launcher takes this instantiation only when every thread
+  // has at most one halo site (setup_halo_prefetch).
   constexpr bool HPF = setup_halo_prefetch<L, T, MODE>();
   const bool hown = HPF && tid < nhalo;
   int hi1 = 0, hi2 = 0;
