@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(AdjGeom g, const T* __restric
                                                    double wp, double wm) {
   constexpr int Q = L::Q, D = L::D;
   const double cs2 = 1.0 / 3.0;
+  const double inv1pa2 = 1.0 / (1.0 + a / 2.0);  // as the forward sweep forms m
   const int64_t NS = g.NS;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < NS; x += stride) {
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(AdjGeom g, const T* __restric
 #pragma unroll
     for (int b = 0; b <= D; ++b) {
       hh[b] = h[b * NS + x];
-      m[b] = (M[b] + hh[b] / 2.0) / (1.0 + a / 2.0);
+      m[b] = (M[b] + 0.5 * hh[b]) * inv1pa2;
       s[b] = hh[b] - a * m[b];
     }
     double lf[Q], gk[Q], pk[Q];
@@ -234,9 +235,10 @@ __global__ void k_extrap_h(int64_t NS, int order, int q, double dt, const T* __r
   using CT = typename CompT<T>::type;
   constexpr int Q = L::Q, D1 = L::D + 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const double inv_dt = 1.0 / dt, inv_2dt = 1.0 / (2.0 * dt);
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += stride) {
     for (int b = 0; b < D1; ++b)
-      h[b * NS + s] = (q == 1) ? mc[b * NS + s] / dt : (4.0 * mc[b * NS + s] - mp[b * NS + s]) / (2.0 * dt);
+      h[b * NS + s] = (q == 1) ? mc[b * NS + s] * inv_dt : (4.0 * mc[b * NS + s] - mp[b * NS + s]) * inv_2dt;
     CT a0[Q], a1[Q], a2[Q];
     site_load<L, T>(f0, NS, s, sig, a0);
     if (order >= 1) site_load<L, T>(f1, NS, s, sig, a1);

@@ -17,6 +17,8 @@ struct AcceptArgs {
   const double* h;
   int64_t NS;
   double a;
+  double inv1pa2;  // 1/(1 + a/2), formed once on the host (the setup sweep's
+                   // reconstruction uses the same value, so both agree bit for bit)
   // 1: the reconstruction of m^{n+1} is left to the next step's setup sweep,
   // which forms it from the same populations (the next step is enqueued by
   // the same call)
@@ -94,7 +96,7 @@ __device__ inline void accept_sites(const AcceptArgs<L, T>& A, int64_t s0, int64
     double M[4];
     site_moments<L, T>(f, NS, s, M);
 #pragma unroll
-    for (int b = 0; b <= L::D; ++b) m[b * NS + s] = (M[b] + A.h[b * NS + s] / 2.0) / (1.0 + A.a / 2.0);
+    for (int b = 0; b <= L::D; ++b) m[b * NS + s] = (M[b] + 0.5 * A.h[b * NS + s]) * A.inv1pa2;
   }
 }
 

@@ -1833,6 +1833,9 @@ class Solver : public SolverBase {
     S.recon = (ell == 1 && recon) ? 1 : 0;
     S.h_prev = h_of(n - 1);
     S.a_prev = a_prev;
+    S.inv1pa2_prev = 1.0 / (1.0 + a_prev / 2.0);
+    S.inv_dt = 1.0 / P.dt;
+    S.inv_2dt = 1.0 / (2.0 * P.dt);
     S.n = n;
     S.ell = ell;
     for (int i = 0; i < 3; ++i) S.mb[i] = mb[i];
@@ -1925,6 +1928,7 @@ class Solver : public SolverBase {
     Ac.h = h_of(n);
     Ac.NS = G.NS;
     Ac.a = a;
+    Ac.inv1pa2 = 1.0 / (1.0 + a / 2.0);
     return Ac;
   }
 

@@ -223,6 +223,8 @@ struct SweepArgs {
   int recon;
   const double* h_prev;
   double a_prev;
+  // reciprocals formed once on the host: 1/(1 + a_prev/2), 1/dt, 1/(2 dt)
+  double inv1pa2_prev, inv_dt, inv_2dt;
   // fused forward row transform (2D, tiles spanning whole rows, Algorithm 1
   // with the shadow corrector): the band spectrum of P r goes to spec
   // ([field][x][j <= N_y/4], as the first transform pass writes it) instead
@@ -411,7 +413,7 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
         }
       }
 #pragma unroll
-      for (int b = 0; b <= D; ++b) mn[b] = (Mn[b] + r.hv[b] / 2.0) / (1.0 + A.a_prev / 2.0);
+      for (int b = 0; b <= D; ++b) mn[b] = (Mn[b] + 0.5 * r.hv[b]) * A.inv1pa2_prev;
       if (mnout) {
 #pragma unroll
         for (int b = 0; b <= D; ++b) mnout[b] = mn[b];
@@ -423,7 +425,7 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
     // Eq. (bdf2) in FP64, and the extrapolated initial trial (Sec. 3.1)
 #pragma unroll
     for (int b = 0; b <= D; ++b)
-      h[b] = (A.q == 1) ? mn[b] / A.dt : (4.0 * mn[b] - r.mpv[b]) / (2.0 * A.dt);
+      h[b] = (A.q == 1) ? mn[b] * A.inv_dt : (4.0 * mn[b] - r.mpv[b]) * A.inv_2dt;
     if constexpr (DV) {
       CT g1[Q], g2[MODE == SW_DTS_SETUP ? Q : 1];
       dev_rebuild<L>(r.f0, r.M0, A.sig, f);
