@@ -328,9 +328,11 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
  * solve, inverse transforms): 0 = automatic (split from N_x = 512), 1 =
  * split, 2 = one fused kernel, 10 = march msc_explicit_step in place by the
  * AA pattern (pairs of steps on one population array; periodic boundaries
- * with FP64 or FP32 storage; 0/1, default 1).  Results do not
+ * with FP64 or FP32 storage; 0/1, default 1), 11 = D3Q19 with N_z = 128: run
+ * the dual-time sweeps after the first of a step on 4 x 128 tiles of 512
+ * threads (0/1, default 1).  Results do not
  * depend on these beyond rounding order (keys 6 = 1 and 2 give identical
- * results; key 10 gives identical results).  MSC_ERR_INVALID_ARG for an
+ * results; keys 10 and 11 give identical populations).  MSC_ERR_INVALID_ARG for an
  * unknown key or value. */
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value);
 

@@ -319,6 +319,10 @@ msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
       if (value < 0 || value > 1) return MSC_ERR_INVALID_ARG;
       t.explicit_aa = value;
       break;
+    case 11:
+      if (value < 0 || value > 1) return MSC_ERR_INVALID_ARG;
+      t.wide_dual = value;
+      break;
     default: return MSC_ERR_INVALID_ARG;
   }
   if (key <= 1 || key >= 5) return fwd(c, c->s->reconfigure());

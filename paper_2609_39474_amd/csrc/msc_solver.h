@@ -38,6 +38,8 @@ struct Tuning {
   int fs_split = 0;          // full-symbol column pass: 0 = automatic, 1 = three kernels
                              // (transforms, solve, transforms), 2 = one fused kernel
   int explicit_aa = 1;       // explicit march in place by the AA pattern where available
+  int wide_dual = 1;         // D3Q19 at N_z = 128: the 4 x 128 tile of 512 threads for the
+                             // dual-time sweeps after the first of a step
 };
 
 class SolverBase {

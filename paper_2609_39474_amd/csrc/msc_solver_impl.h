@@ -1506,8 +1506,9 @@ class Solver : public SolverBase {
     S.N1 = G.N1;
     S.N2 = G.N2;
     S.L = strip_L;
-    S.ntile1 = G.N1 / tile.T1;
-    S.ntile2 = G.N2 / tile.T2;
+    const TileCfg tm = tile_of(SW_DTS);
+    S.ntile1 = G.N1 / tm.T1;
+    S.ntile2 = G.N2 / tm.T2;
     S.nstrip = G.N0 / strip_L;
     S.NS = G.NS;
     S.ctl = nullptr;
@@ -1523,6 +1524,8 @@ class Solver : public SolverBase {
     S.wm = wm;
     if (D == 2)
       launch_sweep_d2<double, double>(tile_id, SW_DTS, S, sweep_grid(), st);
+    else if (wide_mode(SW_DTS))
+      launch_sweep_dual_wide<double, double>(SW_DTS, S, sweep_grid(), st);
     else
       launch_sweep_d3<double, double>(tile_id, SW_DTS, S, sweep_grid(), st);
     MSC_HIPCK(hipGetLastError());
@@ -1617,6 +1620,7 @@ class Solver : public SolverBase {
 
   // ------------------------------------------------------ sweep config --
   int tile_id = 0, strip_L = 1;
+  bool wide_dual = false;  // dual-time sweeps after the first of a step on kWideDualTile3
   int strip_setup = 1;     // planes per strip of the first sweep of a step
   int strip_explicit = 1;  // planes per strip of the tiled explicit sweep
   TileCfg tile{};
@@ -1643,7 +1647,9 @@ class Solver : public SolverBase {
     if (best < 0) best = auto_sweep_tile<L>(G.N1, G.N2);
     tile_id = best;
     tile = TileSet<L>::get(best);
-    strip_L = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_DUAL);
+    wide_dual = D == 3 && tune.wide_dual && tile.T1 == 2 && tile.T2 == 128 && G.N2 == 128 && G.N1 >= 4;
+    strip_L = wide_dual ? sweep_strip_for<L, T>(kWideDualTile3, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_DUAL_WIDE)
+                        : sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_DUAL);
     strip_setup = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_SETUP);
     strip_explicit = sweep_strip_for<L, T>(tile, G.N0, G.N1, G.N2, tune.sweep_strip, STRIP_EXPLICIT);
     fuse_rows = D == 2 && P.corrector == MSC_CORRECTOR_SHADOW && tile.T1 == 1 && tile.T2 == G.N2 &&
@@ -1654,8 +1660,11 @@ class Solver : public SolverBase {
   int strip_of(int mode) const {
     return (mode == SW_DTS_SETUP) ? strip_setup : (mode == SW_EXPLICIT ? strip_explicit : strip_L);
   }
+  bool wide_mode(int mode) const { return wide_dual && (mode == SW_DTS || mode == SW_DTS_LIFT); }
+  TileCfg tile_of(int mode) const { return wide_mode(mode) ? kWideDualTile3 : tile; }
   int sweep_grid(int mode = SW_DTS) const {
-    return (int)((int64_t)(G.N1 / tile.T1) * (G.N2 / tile.T2) * (G.N0 / strip_of(mode)));
+    const TileCfg t = tile_of(mode);
+    return (int)((int64_t)(G.N1 / t.T1) * (G.N2 / t.T2) * (G.N0 / strip_of(mode)));
   }
   int sweep_grid_max() const {
     return std::max({sweep_grid(), sweep_grid(SW_DTS_SETUP), sweep_grid(SW_EXPLICIT)});
@@ -1770,8 +1779,13 @@ class Solver : public SolverBase {
     }
     S.L = strip_of(mode);
     S.nstrip = G.N0 / S.L;
+    const TileCfg tm = tile_of(mode);
+    S.ntile1 = G.N1 / tm.T1;
+    S.ntile2 = G.N2 / tm.T2;
     if (D == 2)
       launch_sweep_d2<T, TM>(tile_id, mode, S, sweep_grid(mode), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
+    else if (wide_mode(mode))
+      launch_sweep_dual_wide<T, TM>(mode, S, sweep_grid(mode), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
     else
       launch_sweep_d3<T, TM>(tile_id, mode, S, sweep_grid(mode), st, timing ? ep.a : nullptr, timing ? ep.b : nullptr);
     MSC_HIPCK(hipGetLastError());

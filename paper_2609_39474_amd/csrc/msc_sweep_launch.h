@@ -99,6 +99,23 @@ void launch_sweep_d3(int tile, int mode, const SweepArgs<T, TM>& A, int grid, hi
   }
 }
 
+// D3Q19 sweeps after the first of a step (SW_DTS, SW_DTS_LIFT) at N_z = 128:
+// a 4 x 128 tile of 512 threads, one halo row per two owned rows instead of
+// one per owned row; one block of eight waves per CU (the FP64 rings take
+// 148 KB of LDS), the occupancy of two 2 x 128 blocks.  The first sweep keeps
+// the 2 x 128 tile (its registers allow one wave per SIMD only).
+constexpr TileCfg kWideDualTile3 = {4, 128, 512};
+template <class T, class TM>
+void launch_sweep_dual_wide(int mode, const SweepArgs<T, TM>& A, int grid, hipStream_t st, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr) {
+  if (mode == SW_DTS)
+    launch_sweep_mode<D3Q19, T, TM, 512, 4, 128, SW_DTS>(A, grid, st, ev0, ev1);
+  else if (mode == SW_DTS_LIFT)
+    launch_sweep_mode<D3Q19, T, TM, 512, 4, 128, SW_DTS_LIFT>(A, grid, st, ev0, ev1);
+  else
+    throw DeviceError{hipErrorInvalidValue, "the wide dual-time tile serves SW_DTS and SW_DTS_LIFT only"};
+}
+
 // Automatic tile: the largest tile that fits (measured best at every size;
 // the strip length supplies the parallelism).  3D: at N_z = 128 the 2 x 128
 // tile, which spans z and so has no z halo (measured at N = 128: 5% per step
@@ -155,7 +172,9 @@ int auto_sweep_tile(int N1, int N2) {
 // one wave of 256 blocks then keeps every tile of a strip resident on its XCD,
 // so the halo rows a block re-collides are its neighbours' rows in that XCD's
 // L2 (the setup sweep read 2.0x its algorithmic bytes with 512 blocks).
-enum StripKind { STRIP_EXPLICIT = 0, STRIP_DUAL = 1, STRIP_SETUP = 2 };
+//
+// STRIP_DUAL_WIDE (the 512-thread dual-time tile, one block per CU): 256 blocks.
+enum StripKind { STRIP_EXPLICIT = 0, STRIP_DUAL = 1, STRIP_SETUP = 2, STRIP_DUAL_WIDE = 3 };
 
 template <class L, class T>
 int sweep_strip_for(const TileCfg& tile, int N0, int N1, int N2, int requested, StripKind kind) {
@@ -166,7 +185,7 @@ int sweep_strip_for(const TileCfg& tile, int N0, int N1, int N2, int requested, 
     if (L::D == 2)
       target = (kind == STRIP_EXPLICIT) ? 1024 : 512;
     else
-      target = (kind == STRIP_SETUP && sizeof(T) == 8) ? 256 : 512;
+      target = ((kind == STRIP_SETUP && sizeof(T) == 8) || kind == STRIP_DUAL_WIDE) ? 256 : 512;
     const int Lmax = (L::D == 2) ? 64 : 32;
     Lp = 1;
     while (Lp < Lmax && tiles * (N0 / (Lp * 2)) >= target) Lp *= 2;
