@@ -44,12 +44,13 @@ __host__ __device__ constexpr bool setup_mode(int m) { return m == SW_DTS_SETUP 
 // first sweep whose halo loads are issued a plane ahead (see k_sweep)
 template <class L, class T, int MODE>
 __host__ __device__ constexpr bool setup_halo_prefetch() {
-  return MODE == SW_DTS_SETUP1 && L::D == 3;
+  return MODE == SW_DTS_SETUP1 && L::D == 3 && sizeof(T) != 4;
 }
 // sweep whose owned loads for the next plane are issued after the halo (see k_sweep)
 template <class L, class T, int MODE>
 __host__ __device__ constexpr bool late_owned_prefetch() {
-  return (MODE == SW_DTS || MODE == SW_DTS_LIFT) && L::D == 3 && sizeof(T) == 8;
+  return L::D == 3 && (((MODE == SW_DTS || MODE == SW_DTS_LIFT) && sizeof(T) == 8) ||
+                       (MODE == SW_DTS_SETUP1 && sizeof(T) == 4));
 }
 // halo ring sites of a T1 x T2 tile (one ring along each axis the tile does
 // not span)
@@ -600,11 +601,15 @@ __device__ __forceinline__ void collide_raw(const SweepArgs<T, TM>& A, const Raw
 // block per CU runs anyway).
 // The D2Q9 FP32 dual-time and lift sweeps need 129-131 registers, one or
 // three above the 128 that allow four waves per SIMD; bounded to four.
+// The D3Q19 FP32 first sweep (order-1 trial, owned loads issued late) fits
+// two waves with 12 bytes of spills per lane: N = 128 march 0.474 -> 0.441 ms
+// per step against one wave with the halo prefetch.
 template <class L, class T, int MODE, int T1>
 __host__ __device__ constexpr int sweep_min_waves() {
   return (L::D == 2 && sizeof(T) == 8 && setup_mode(MODE))                              ? 2
          : (L::D == 2 && sizeof(T) == 4 && (MODE == SW_DTS || MODE == SW_DTS_LIFT)) ? 4
          : (sweep_two_barriers<L, T>() && !setup_mode(MODE) && T1 > 1)                 ? 2
+         : (L::D == 3 && sizeof(T) == 4 && MODE == SW_DTS_SETUP1 && T1 > 1)           ? 2
                                                                                        : 1;
 }
 
@@ -703,18 +708,21 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
       load_raw<L, T, TM, MODE>(A, P, ((int64_t)xs0 * N1 + (b1 + i1)) * N2 + (b2 + i2), raw[j]);
     }
   }
-  // The D3Q19 first sweep runs one wave per SIMD in every storage type
-  // (history states and the FP64 collision in flight), so nothing would hide
-  // the latency of its halo loads: they are issued one plane ahead like the
-  // owned ones.  The launcher takes this instantiation only when every thread
-  // has at most one halo site (setup_halo_prefetch).
+  // The D3Q19 first sweep with FP64 and FP16-deviation storage runs one wave
+  // per SIMD (history states and the FP64 collision in flight), so nothing
+  // would hide the latency of its halo loads: they are issued one plane ahead
+  // like the owned ones.  The launcher takes this instantiation only when
+  // every thread has at most one halo site (setup_halo_prefetch).  With FP32
+  // storage the first sweep fits two waves per SIMD instead, with the owned
+  // loads issued late (below).
   constexpr bool HPF = setup_halo_prefetch<L, T, MODE>();
   // D3Q19 FP64 sweeps after the first of a step: the owned sites' loads for
   // the next plane are issued after this plane's halo sites, so that a block
   // fetches its halo rows soon after the neighbouring blocks fetched the same
   // rows as owned ones (more of them still in L2): N = 128 march 0.760 ->
-  // 0.745 ms per step; FP32 storage, with a third of the traffic per site,
-  // gains nothing
+  // 0.745 ms per step (FP32 sweeps after the first gain nothing).  The FP32
+  // first sweep issues them late too: no loads in flight during the
+  // collision, which brings it to 256 registers and two waves per SIMD
   constexpr bool LATE = late_owned_prefetch<L, T, MODE>();
   const bool hown = HPF && tid < nhalo;
   int hi1 = 0, hi2 = 0;
