@@ -3,8 +3,8 @@ against the FP64 oracle at 1e-12 per field, or ten times the oracle's own
 one-ulp sensitivity of the field where that is larger): the row transforms of the correction fused
 into the sweep (forward only, or forward and inverse) or run as their own
 passes, sweep tiles and strip lengths other than the automatic choice, the
-folded-partials path of large sweep grids, and every D3Q19 tile of the
-library's table.  Results must not depend on these choices beyond rounding
+folded-partials path of large sweep grids, every D3Q19 tile of the library's
+table, and the 512-thread tile of the D3Q19 dual-time sweeps at N_z = 128.  Results must not depend on these choices beyond rounding
 order; the two fused variants run the same arithmetic and agree bit for bit.
 """
 import sys
@@ -167,3 +167,43 @@ def test_d3q19_tiles(M, orc, idx):
     say("3D tile index", idx, "correct", rel(fn, ofn), "step", rel(g, st1))
     assert rel(g, st1) <= 1e-12
     s.close()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_wide_dual_tile(M, orc, storage):
+    """D3Q19 at N_z = 128: the sweeps after the first of a step on 4 x 128
+    tiles of 512 threads (key 11 = 1, the default) and on the 2 x 128 tiles
+    (key 11 = 0) give the same counts and bit-identical states over three
+    steps (the per-site arithmetic is the same; only the halo rows each block
+    re-collides differ); with FP64 storage one corrected iteration on the wide
+    tile matches the oracle at 1e-12."""
+    shape = (16, 8, 128)
+    u1 = np.tile(W.random_perturbation_3d(8, 1e-3, seed=5, jmax=2), (1, 2, 1, 16))
+    p0 = np.zeros(shape)
+    states, counts = {}, {}
+    for wide in (0, 1):
+        p = M.make_params(3, shape[0], dt=32.0, eps=1e-10, storage=storage, n_min=2, extrap_states=2)
+        for a in range(3):
+            p.n[a] = shape[a]
+        s = M.Solver(p, p0, u1)
+        s.set_tuning(11, wide)
+        if wide == 1:
+            s.set_schedule(counts[0])
+        rc, st = s.bdf2_step(3)
+        assert rc == 0
+        counts[wide] = [x["iters"] for x in st]
+        states[wide], _ = s.get_state()
+        if wide == 1 and storage == "fp64":
+            rng = np.random.default_rng(7)
+            c, w, _ = orc.lattice(3)
+            wq = w.reshape((19, 1, 1, 1))
+            f = wq * (1e-3 * rng.normal(size=(19,) + shape)) + wq * 0.01 * rng.normal(size=shape)
+            h = 1e-4 * rng.normal(size=(4,) + shape)
+            fn, dm, R = s.correct(f, h, 3.0 / 64.0)
+            ofn, _, _, odm, oR = orc.corrected_iteration(f, h, 3.0 / 64.0, 1.0, 1.0, NU)
+            say("wide tile correct: rel f", rel(fn, ofn), "dm", rel_fields(dm, odm))
+            assert rel_fields(dm, odm) <= 1e-12 and rel(fn, ofn) <= 1e-12 and abs(R - oR) <= 1e-12 * oR
+        s.close()
+    say(storage, "wide dual tile: counts", counts[1], "2 x 128:", counts[0])
+    assert counts[0] == counts[1]
+    assert np.array_equal(states[0], states[1])
