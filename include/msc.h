@@ -188,7 +188,11 @@ msc_status msc_bdf2_step(msc_ctx* c, int32_t nsteps, msc_step_stats* stats);
 
 /* Advance nsteps lattice steps of the source-free TRT map (the sweep with
  * a = 0, h = 0: m = P f, no source; Sec. 4.1: the explicit baseline uses the
- * same collision and streaming kernels).  Resets the BDF history: the next
+ * same collision and streaming).  With periodic boundaries and FP64 or FP32
+ * storage the march runs in place by the AA access pattern (pairs of steps on
+ * one population array; an odd count ends with one step of the two-buffer
+ * sweep), otherwise on the two-buffer sweep; both give identical results
+ * (msc_set_tuning key 10).  Resets the BDF history: the next
  * msc_bdf2_step is BDF1 from the current state with m^n = P f^n.
  * Errors: MSC_ERR_INVALID_ARG (nsteps < 0); MSC_ERR_NONFINITE when the final
  * state holds a non-finite value (checked once at the end). */
