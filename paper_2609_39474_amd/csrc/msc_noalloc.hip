@@ -94,8 +94,11 @@ msc_status run(const int* n, double tau_plus, double tau_minus, const T* f, cons
   const int N2 = (L::D == 2) ? n[1] : n[2];
   const int64_t NS = (int64_t)N0 * N1 * N2;
   const int tile_id = auto_sweep_tile<L>(N1, N2);
-  const TileCfg tile = TileSet<L>::get(tile_id);
-  const int strip = sweep_strip_for<L, T>(tile, N0, N1, N2, 0, STRIP_DUAL);
+  const TileCfg base = TileSet<L>::get(tile_id);
+  // the wide dual-time tile where a context takes it (D3Q19, N_z = 128)
+  const bool wide = L::D == 3 && base.T1 == 2 && base.T2 == 128 && N2 == 128 && N1 >= 4;
+  const TileCfg tile = wide ? kWideDualTile3 : base;
+  const int strip = sweep_strip_for<L, T>(tile, N0, N1, N2, 0, wide ? STRIP_DUAL_WIDE : STRIP_DUAL);
   const int64_t grid = (int64_t)(N1 / tile.T1) * (N2 / tile.T2) * (N0 / strip);
   if (grid > kScratchDoubles) return MSC_ERR_INVALID_ARG;
   double* parts = nullptr;
@@ -122,7 +125,14 @@ msc_status run(const int* n, double tau_plus, double tau_minus, const T* f, cons
   S.wm = 1.0 / tau_minus;
   S.sig = 1.0f;
   S.isig = 1.0f;
-  launch_dts<T>(L::D, tile_id, S, (int)grid, st);
+  if constexpr (L::D == 3) {
+    if (wide)
+      launch_sweep_dual_wide<T, T>(SW_DTS, S, (int)grid, st);
+    else
+      launch_dts<T>(L::D, tile_id, S, (int)grid, st);
+  } else {
+    launch_dts<T>(L::D, tile_id, S, (int)grid, st);
+  }
   if (hipGetLastError() != hipSuccess) return MSC_ERR_DEVICE;
   if (R) {
     hipLaunchKernelGGL(k_noalloc_rms, dim3(1), dim3(256), 0, st, parts, (int)grid, 1.0 / ((double)L::Q * (double)NS),

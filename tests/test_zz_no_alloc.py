@@ -40,6 +40,9 @@ CASES = [
     (2, "fp32", (256, 256), (64, 32)),
     (3, "fp64", (16, 16, 32), (8, 8, 8)),
     (3, "fp32", (32, 32, 64), (8, 16, 8)),
+    # N_z = 128: the wide dual-time tile (4 x 128 sites, 512 threads)
+    (3, "fp64", (8, 8, 128), (4, 4, 16)),
+    (3, "fp32", (16, 4, 128), (8, 8, 128)),
 ]
 
 
