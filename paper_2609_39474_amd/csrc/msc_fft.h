@@ -307,17 +307,23 @@ struct Fft3Args {
 
 __device__ inline int band_to_j(int i, int N, int NB) { return (i <= N / 4) ? i : N - (NB - i); }
 
-// pass 1: forward along z of pencils (x, y); fields (0,1) and (2,3) packed
+// pass 1: forward along z of pencils (x, y); fields (0,1) and (2,3) packed.
+// The grid holds as many blocks as the device runs at once and each block
+// loops over groups of R pencils, so that the acceptance decision (a chain
+// of dependent loads) is taken once per block rather than once per group.
 template <class L, class T, class CT, class TM>
 __global__ __launch_bounds__(256) void k_fft3_z_fwd(Fft3Args<CT, TM> A, AcceptArgs<L, T> Ac, FinishArgs Fin) {
   const int R = A.pencils_per_block, Nz = A.Nz;
+  const int ngrp = (A.Nx * A.Ny) / R;
   if (A.do_accept) {
     __shared__ double red[256];
     const int dec = finish_block(Fin, red);
     if (dec != DEC_RUNNING) {
       if (dec == DEC_ACCEPTED) {
-        const int64_t s0 = (int64_t)blockIdx.x * R * Nz;
-        accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)R * Nz, blockDim.x);
+        for (int g = blockIdx.x; g < ngrp; g += gridDim.x) {
+          const int64_t s0 = (int64_t)g * R * Nz;
+          accept_sites<L, T>(Ac, s0 + threadIdx.x, s0 + (int64_t)R * Nz, blockDim.x);
+        }
       }
       return;
     }
@@ -327,27 +333,30 @@ __global__ __launch_bounds__(256) void k_fft3_z_fwd(Fft3Args<CT, TM> A, AcceptAr
   extern __shared__ unsigned char smem_raw[];
   cpx<CT>* buf = reinterpret_cast<cpx<CT>*>(smem_raw);
   cpx<CT>* tmp = buf + 2 * R * Nz;
-  const int64_t p0 = (int64_t)blockIdx.x * R;
   const int64_t NS = (int64_t)A.Nx * A.Ny * Nz;
-  for (int i = threadIdx.x; i < R * Nz; i += blockDim.x) {
-    const int r = i / Nz, z = i - r * Nz;
-    const int64_t s = (p0 + r) * Nz + z;
-    buf[(2 * r) * Nz + z] = {(CT)A.Pr[s], (CT)A.Pr[NS + s]};
-    buf[(2 * r + 1) * Nz + z] = {(CT)A.Pr[2 * NS + s], (CT)A.Pr[3 * NS + s]};
-  }
-  __syncthreads();
-  const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgz, 2 * R, -1, A.twz);
   const int NB = A.NBz;
   const int64_t FS = (int64_t)A.Nx * A.Ny * NB;
-  for (int i = threadIdx.x; i < R * NB; i += blockDim.x) {
-    const int r = i / NB, j = i - r * NB;
-    const int64_t o = (p0 + r) * NB + j;
-    for (int h = 0; h < 2; ++h) {
-      const cpx<CT> z = out[(2 * r + h) * Nz + j];
-      const cpx<CT> zc = out[(2 * r + h) * Nz + ((Nz - j) & (Nz - 1))];
-      A.spec1[(2 * h) * FS + o] = {(CT)0.5 * (z.x + zc.x), (CT)0.5 * (z.y - zc.y)};
-      A.spec1[(2 * h + 1) * FS + o] = {(CT)0.5 * (z.y + zc.y), (CT)0.5 * (zc.x - z.x)};
+  for (int g = blockIdx.x; g < ngrp; g += gridDim.x) {
+    const int64_t p0 = (int64_t)g * R;
+    for (int i = threadIdx.x; i < R * Nz; i += blockDim.x) {
+      const int r = i / Nz, z = i - r * Nz;
+      const int64_t s = (p0 + r) * Nz + z;
+      buf[(2 * r) * Nz + z] = {(CT)A.Pr[s], (CT)A.Pr[NS + s]};
+      buf[(2 * r + 1) * Nz + z] = {(CT)A.Pr[2 * NS + s], (CT)A.Pr[3 * NS + s]};
     }
+    __syncthreads();
+    const cpx<CT>* out = lds_fft<CT>(buf, tmp, A.lgz, 2 * R, -1, A.twz);
+    for (int i = threadIdx.x; i < R * NB; i += blockDim.x) {
+      const int r = i / NB, j = i - r * NB;
+      const int64_t o = (p0 + r) * NB + j;
+      for (int h = 0; h < 2; ++h) {
+        const cpx<CT> z = out[(2 * r + h) * Nz + j];
+        const cpx<CT> zc = out[(2 * r + h) * Nz + ((Nz - j) & (Nz - 1))];
+        A.spec1[(2 * h) * FS + o] = {(CT)0.5 * (z.x + zc.x), (CT)0.5 * (z.y - zc.y)};
+        A.spec1[(2 * h + 1) * FS + o] = {(CT)0.5 * (z.y + zc.y), (CT)0.5 * (zc.x - z.x)};
+      }
+    }
+    __syncthreads();  // buf and tmp are refilled by the next group
   }
 }
 

@@ -4,7 +4,8 @@ one-ulp sensitivity of the field where that is larger): the row transforms of th
 into the sweep (forward only, or forward and inverse) or run as their own
 passes, sweep tiles and strip lengths other than the automatic choice, the
 folded-partials path of large sweep grids, every D3Q19 tile of the library's
-table, and the 512-thread tile of the D3Q19 dual-time sweeps at N_z = 128.  Results must not depend on these choices beyond rounding
+table, the 512-thread tile of the D3Q19 dual-time sweeps at N_z = 128, and
+the pencils and columns per block of the 3D transform passes.  Results must not depend on these choices beyond rounding
 order; the two fused variants run the same arithmetic and agree bit for bit.
 """
 import sys
@@ -207,3 +208,42 @@ def test_wide_dual_tile(M, orc, storage):
     say(storage, "wide dual tile: counts", counts[1], "2 x 128:", counts[0])
     assert counts[0] == counts[1]
     assert np.array_equal(states[0], states[1])
+
+
+KEY_FFT3_PENCILS, KEY_FFT3_COLS = 7, 8
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_transform_shapes_3d(M, orc, storage):
+    """The 3D correction's launch shapes: z pencils per block (key 7; the
+    forward z pass loops over pencil groups on a grid of resident blocks) and
+    j_z columns per block of the y and x passes (key 8, widths that divide the
+    9 band columns of N_z = 32 unevenly and evenly) leave the corrected
+    iteration bit-identical; with FP64 storage the automatic shape matches the
+    oracle at 1e-12 per field."""
+    shape = (16, 32, 32)
+    rng = np.random.default_rng(21)
+    c, w, _ = orc.lattice(3)
+    wq = w.reshape((19, 1, 1, 1))
+    f = wq * (1e-3 * rng.normal(size=(19,) + shape)) + wq * 0.01 * rng.normal(size=shape)
+    h = 1e-4 * rng.normal(size=(4,) + shape)
+    a = 3.0 / 64.0
+    p = M.make_params(3, shape[0], dt=32.0, eps=1e-10, storage=storage, n_min=2)
+    for ax in range(3):
+        p.n[ax] = shape[ax]
+    s = M.Solver(p, np.zeros(shape), np.zeros((3,) + shape))
+    ref = None
+    for pencils, cols in [(0, 0), (1, 1), (2, 3), (4, 4), (4, 8), (1, 5), (2, 2)]:
+        s.set_tuning(KEY_FFT3_PENCILS, pencils)
+        s.set_tuning(KEY_FFT3_COLS, cols)
+        fn, dm, R = s.correct(f, h, a)
+        say(storage, "3D transform shape: pencils", pencils, "cols", cols, "R", R)
+        if ref is None:
+            ref = (fn, dm, R)
+            if storage == "fp64":
+                ofn, _, _, odm, oR = orc.corrected_iteration(f, h, a, 1.0, 1.0, NU)
+                say("  vs oracle: rel f", rel(fn, ofn), "dm", rel_fields(dm, odm))
+                assert rel_fields(dm, odm) <= 1e-12 and rel(fn, ofn) <= 1e-12 and abs(R - oR) <= 1e-12 * oR
+        else:
+            assert np.array_equal(fn, ref[0]) and np.array_equal(dm, ref[1]) and R == ref[2]
+    s.close()
