@@ -247,3 +247,57 @@ def test_transform_shapes_3d(M, orc, storage):
         else:
             assert np.array_equal(fn, ref[0]) and np.array_equal(dm, ref[1]) and R == ref[2]
     s.close()
+
+
+@pytest.mark.parametrize("shape,storage", [((4, 4, 128), "fp64"), ((4, 4, 128), "fp32"), ((4, 8, 128), "fp64")])
+def test_small_y_extent_at_nz128(M, orc, shape, storage):
+    """D3Q19 at N_z = 128 with the smallest y extents: N_y = 4, where the 4 x
+    128 tile of the dual-time sweeps after the first spans y as well (no halo
+    rows, streaming wraps inside the tile) and the first sweep's two 2 x 128
+    tiles take their halo rows from each other, and N_y = 8.  Four corrected
+    BDF steps against the oracle's march with the same inner counts.  FP64:
+    the final populations and moments per field within 1e-12 or ten times the
+    oracle's own one-ulp sensitivity; FP32: the RMS error of each velocity
+    component within 1e-5 of that component's RMS."""
+    # every component dominated by slow modes along z (|k| = 2 pi/128, 4 pi/128)
+    # with smaller parts along x and y: on 4-site extents those sit at |k| =
+    # pi/2, decay by ~e^-52 over the four steps and would leave a relative
+    # error measured against a vanished field
+    x, y, z = np.meshgrid(*[np.arange(n) / n for n in shape], indexing="ij")
+    tp = 2.0 * np.pi
+    u1 = 1e-3 * np.stack([np.sin(tp * z) + 0.2 * np.cos(tp * x) * np.sin(tp * z),
+                          0.5 * np.cos(tp * z) + 0.2 * np.sin(tp * y),
+                          0.3 * np.sin(2 * tp * z) + 0.2 * np.sin(tp * x)])
+    p0 = np.zeros(shape)
+    p = M.make_params(3, shape[0], dt=32.0, eps=1e-10 if storage == "fp64" else 1e-8, storage=storage,
+                      n_min=2, extrap_states=2)
+    for a in range(3):
+        p.n[a] = shape[a]
+    st0 = orc.initial_state(p0, u1)
+    kw = dict(dt=32.0, nsteps=4, eps=1e-10, nmin=2, extrap_states=2)
+    rc, ref, _, ost = orc.march_state(st0, 0, shape, **kw)
+    assert rc == 0
+    K = [x["iters"] for x in ost]
+    s = M.Solver(p, p0, u1)
+    s.set_schedule(K)
+    rc, st = s.bdf2_step(4)
+    assert rc == 0 and [x["iters"] for x in st] == K
+    state, _ = s.get_state()
+    s.close()
+    NS = int(np.prod(shape))
+    FQ, FM = 19 * NS, 4 * NS
+    say(storage, shape, "small y extent at N_z = 128: counts", K)
+    if storage == "fp64":
+        _, alt, _, _ = orc.march_state(PB.ulp_perturbed(st0, 0), 0, shape, schedule=K, **kw)
+        for lo, hi, nf, what in ((0, FQ, 1, "f^n"), (3 * FQ, 3 * FQ + FM, 4, "m^n")):
+            errs = PB.field_rels(state[lo:hi], ref[lo:hi], nf)
+            say("  vs oracle:", what, errs)
+            PB.check_fields(errs, PB.sensitivity_bars(PB.field_rels(alt[lo:hi], ref[lo:hi], nf)), what)
+    else:
+        u = state[3 * FQ + NS:3 * FQ + FM].reshape(3, -1)
+        uref = ref[3 * FQ + NS:3 * FQ + FM].reshape(3, -1)
+        # RMS error of each velocity component relative to the reference
+        # component's RMS (the FP32 precision bar's measure), worst component
+        err = max(float(np.sqrt(np.mean((u[i] - uref[i]) ** 2) / np.mean(uref[i] ** 2))) for i in range(3))
+        say("  fp32 velocity error", err, "max-norm", max(rel(u[i], uref[i]) for i in range(3)))
+        assert err <= 1e-5
