@@ -292,7 +292,10 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
 // 3 = speculative extra iterations, 4 = graph capture of explicit chunks,
 // 5 = tile by table index, 6 = row transforms inside the sweep (0/1/2),
 // 7 / 8 = pencils / columns per block of the 3D transform passes, 9 = the
-// full-symbol column pass split in three kernels (0 auto / 1 split / 2 fused).
+// full-symbol column pass split in three kernels (0 auto / 1 split / 2 fused),
+// 10 = the in-place (AA) explicit march, 11 = the 512-thread D3Q19 dual-time
+// tile at N_z = 128, 12 = the last lift sweep enqueued for a 3D step leaving
+// P r out (formed afterwards only if the step goes on).
 // Keys 0, 1 and 5-8 re-pick the launch shapes at once; the others apply
 // from the next call.
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
@@ -322,6 +325,10 @@ msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {
     case 11:
       if (value < 0 || value > 1) return MSC_ERR_INVALID_ARG;
       t.wide_dual = value;
+      break;
+    case 12:
+      if (value < 0 || value > 1) return MSC_ERR_INVALID_ARG;
+      t.skip_pr = value;
       break;
     default: return MSC_ERR_INVALID_ARG;
   }

@@ -290,6 +290,7 @@ template <class CT, class TM>
 struct Fft3Args {
   CorrGuard g;
   int do_accept;
+  int decide_only;  // with do_accept: take the decision only (the sweep left P r out)
   int adjoint;
   int Nx, Ny, Nz, lgx, lgy, lgz;
   int NBz;  // N_z/4 + 1
@@ -327,6 +328,7 @@ __global__ __launch_bounds__(256) void k_fft3_z_fwd(Fft3Args<CT, TM> A, AcceptAr
       }
       return;
     }
+    if (A.decide_only) return;
   } else if (A.g.skip()) {
     return;
   }

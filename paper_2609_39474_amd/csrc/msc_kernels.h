@@ -109,6 +109,67 @@ __global__ __launch_bounds__(256) void k_accept(AcceptArgs<L, T> A, FinishArgs F
   accept_sites<L, T>(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, A.NS, (int64_t)gridDim.x * blockDim.x);
 }
 
+// P r of a lift sweep that left it out (the sweep enqueued as the last of its
+// step, which then went on): from the sweep's input (the previous f_T), the
+// correction it lifted and its output, by the sweep's own arithmetic (the
+// trial f_in + E dm of Eq. lift, r = f_T - trial, P r summed over k in order),
+// so the values equal those the sweep would have stored.
+template <class T, class TM>
+struct PrArgs {
+  const DevCtl* ctl;
+  int n, ell;
+  FBufs<T> fb;
+  const TM* dm;
+  TM* Pr;
+  int64_t NS;
+};
+
+template <class L, class CT, class TM>
+__device__ __forceinline__ void lifted_trial(const CT* fin, const TM* dmv, CT* f) {
+#pragma clang fp contract(on)
+  const CT d0 = (CT)dmv[0];
+#pragma unroll
+  for (int k = 0; k < L::Q; ++k) {
+    CT cu = 0;
+#pragma unroll
+    for (int b = 0; b < L::D; ++b) cu += (CT)ca<L>(k, b) * (CT)dmv[1 + b];
+    f[k] = fin[k];
+    f[k] += (CT)L::w(k) * (d0 + (CT)3 * cu);
+  }
+}
+
+template <class L, class T, class TM>
+__global__ __launch_bounds__(256) void k_recompute_pr(PrArgs<T, TM> A) {
+  static_assert(!PopDev<T>::value, "deviation storage forms P r from its stored moments");
+  using CT = typename CompT<T>::type;
+  constexpr int Q = L::Q, D = L::D;
+  if (!phase_correct(A.ctl->phase, A.n, A.ell)) return;  // uniform for the grid
+  const Roles& ro = A.ctl->roles[A.n & 1];
+  const T* fin = A.fb.p[ro.slot_w[(A.ell - 1) & 1]];
+  const T* fout = A.fb.p[ro.slot_w[A.ell & 1]];
+  const int64_t NS = A.NS;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < NS; s += (int64_t)gridDim.x * blockDim.x) {
+    CT f0[Q], f[Q];
+    TM dmv[D + 1];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) f0[k] = (CT)fin[(int64_t)k * NS + s];
+#pragma unroll
+    for (int b = 0; b <= D; ++b) dmv[b] = A.dm[b * NS + s];
+    lifted_trial<L, CT, TM>(f0, dmv, f);
+    CT pr[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const CT r = (CT)fout[(int64_t)k * NS + s] - f[k];
+      pr[0] += r;
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb)
+        if (ca<L>(k, bb) != 0) pr[1 + bb] += (CT)ca<L>(k, bb) * r;
+    }
+#pragma unroll
+    for (int bb = 0; bb <= D; ++bb) A.Pr[bb * NS + s] = (TM)pr[bb];
+  }
+}
+
 // ------------------------------------------------------ initialisation --
 // f = feq(p, u) (Eq. feq) from FP64 fields; the initial state of Sec. 4.1.
 // Deviation storage: g = 0 and M = (p, u) (P feq(p, u) = (p, u)).

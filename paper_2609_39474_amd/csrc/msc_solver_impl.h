@@ -1125,6 +1125,12 @@ class Solver : public SolverBase {
   bool corrector_supported() const { return fft_fits(); }
 
   bool fullsym() const { return P.corrector == MSC_CORRECTOR_FULL_SYMBOL; }
+  // 3D shadow corrector with FP64 or FP32 populations: the lift sweep
+  // enqueued as the last of its step leaves P r out (the step is predicted to
+  // accept there); k_recompute_pr forms it if the step goes on
+  bool skip_pr_ok() const {
+    return D == 3 && tune.skip_pr != 0 && P.corrector == MSC_CORRECTOR_SHADOW && !PopDev<T>::value;
+  }
   bool wallkin() const { return P.corrector == MSC_CORRECTOR_WALL_KINETIC; }
   bool walls() const { return P.boundary == MSC_BOUNDARY_CAVITY; }
   bool wall_supported() const {
@@ -1773,7 +1779,7 @@ class Solver : public SolverBase {
     (void)kind;
     if (timing) {
       ep = timed_pair((mode == SW_EXPLICIT) ? 1 : 0,
-                      sweep_bytes(mode, S.order, S.q) +
+                      sweep_bytes(mode, S.order, S.q) - (S.skip_pr ? (double)(D + 1) * G.NS * sizeof(TM) : 0.0) +
                           ((mode == SW_DTS_SETUP && S.recon) ? (double)(D + 1) * G.NS * 8.0 : 0.0));
       S.did_run = run_flags + ep.flag;
     }
@@ -1880,6 +1886,8 @@ class Solver : public SolverBase {
       mode = SW_DTS;
     F.nparts = sweep_grid(mode);
     if (fullsym() || wallkin()) S.rout = rfs;
+    const bool skip_pr = skip_pr_ok() && last && mode == SW_DTS_LIFT;
+    S.skip_pr = skip_pr ? 1 : 0;
     if (fuse_rows) {
       S.fuse_rows = 1;
       S.lgr = ilog2(G.N2);
@@ -1901,7 +1909,7 @@ class Solver : public SolverBase {
     Ac.defer = defer ? 1 : 0;
     if (P.corrector == MSC_CORRECTOR_SHADOW) {
       XformBufs<CT, TM> B{Pr, dm, spec_of(ell), spec2, {tw[0], tw[1], tw[2]}};
-      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last && !fuse_inv, fuse_rows);
+      enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, &F, true, !last && !fuse_inv, fuse_rows, skip_pr);
     } else if (fullsym()) {
       enqueue_fullsym(ctl, n, ell, a, &Ac, &F, true, !last, nullptr);
     } else {
@@ -1920,6 +1928,18 @@ class Solver : public SolverBase {
     if (P.corrector != MSC_CORRECTOR_SHADOW) return;
     if (fuse_inv) return;  // the next sweep inverts the rows itself
     XformBufs<CT, TM> B{Pr, dm, spec_of(ell), spec2, {tw[0], tw[1], tw[2]}};
+    if constexpr (!PopDev<T>::value) {
+      // the tail follows the last sweep enqueued for the step; a lift sweep
+      // there left P r out: form it, then every pass, the first one guarded
+      // rather than deciding (the decision was taken)
+      if (skip_pr_ok() && ell >= 2) {
+        PrArgs<T, TM> R{ctl, n, ell, fb, dm, Pr, G.NS};
+        hipLaunchKernelGGL((k_recompute_pr<L, T, TM>), dim3(ew_grid()), dim3(256), 0, st, R);
+        MSC_HIPCK(hipGetLastError());
+        enqueue_transform<CT, TM>(ctl, n, ell, a, nullptr, false, B, nullptr, true, true, false);
+        return;
+      }
+    }
     AcceptArgs<L, T> Ac = accept_args(n, ell, a);
     enqueue_transform<CT, TM>(ctl, n, ell, a, &Ac, false, B, nullptr, false, true, fuse_rows);
   }
@@ -2169,7 +2189,7 @@ class Solver : public SolverBase {
   template <class CX, class TX>
   void enqueue_transform(const DevCtl* c, int n, int ell, double a, const AcceptArgs<L, T>* Ac, bool adjoint,
                          const XformBufs<CX, TX>& B, const FinishArgs* Fin = nullptr, bool head = true,
-                         bool tail = true, bool rows_in_sweep = false) {
+                         bool tail = true, bool rows_in_sweep = false, bool decide_only = false) {
     AcceptArgs<L, T> none{};
     const FinishArgs nofin{};
     const size_t cb = sizeof(cpx<CX>);
@@ -2234,6 +2254,7 @@ class Solver : public SolverBase {
       Fft3Args<CX, TX> F{};
       F.g = CorrGuard{c, n, ell};
       F.do_accept = Ac ? 1 : 0;
+      F.decide_only = (Ac && decide_only) ? 1 : 0;
       F.adjoint = adjoint ? 1 : 0;
       F.Nx = G.n[0];
       F.Ny = G.n[1];

@@ -239,6 +239,9 @@ struct SweepArgs {
   // D2Q9 lid-driven cavity: wall rows after streaming (every mode)
   int walls;
   double ulid;
+  // lift mode: leave P r out (the sweep predicted to end its step; if the
+  // step goes on, k_recompute_pr forms it from this sweep's input and output)
+  int skip_pr;
 };
 
 // ---- compile-time direction classification -----------------------------
@@ -983,7 +986,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
             // the row of P r (fields 0 and 1 packed in one complex line, field 2 in a second)
             fbuf[i2] = {pr[0], pr[1]};
             fbuf[T2 + i2] = {pr[2], (CT)0};
-          } else if (!A.rout) {
+          } else if (!A.rout && !A.skip_pr) {
 #pragma unroll
             for (int bb = 0; bb <= D; ++bb) __builtin_nontemporal_store((TM)pr[bb], &A.Pr[bb * NS + site]);
           }

@@ -301,3 +301,40 @@ def test_small_y_extent_at_nz128(M, orc, shape, storage):
         err = max(float(np.sqrt(np.mean((u[i] - uref[i]) ** 2) / np.mean(uref[i] ** 2))) for i in range(3))
         say("  fp32 velocity error", err, "max-norm", max(rel(u[i], uref[i]) for i in range(3)))
         assert err <= 1e-5
+
+
+KEY_SKIP_PR = 12
+
+
+@pytest.mark.parametrize("shape", [(16, 8, 128), (8, 8, 32)])
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_last_lift_sweep_without_pr(M, orc, storage, shape):
+    """3D: the lift sweep enqueued as the last of its step leaves P r out
+    (key 12 = 1, the default); when the step goes on, P r is formed from that
+    sweep's input, the correction it lifted and its output before the
+    correction runs.  A free-running march (no replayed counts: the first step
+    needs far more sweeps than predicted, so P r is formed several times)
+    gives the same counts, the same residuals and bit-identical states as
+    with P r always stored (key 12 = 0)."""
+    reps = (1, shape[0] // 8, shape[1] // 8, shape[2] // 8)
+    u1 = np.tile(W.random_perturbation_3d(8, 1e-3, seed=5, jmax=2), reps)
+    p0 = np.zeros(shape)
+    states, counts, stats = {}, {}, {}
+    for skip in (0, 1):
+        p = M.make_params(3, shape[0], dt=32.0, eps=1e-10, storage=storage, n_min=2, extrap_states=2)
+        for a in range(3):
+            p.n[a] = shape[a]
+        s = M.Solver(p, p0, u1)
+        s.set_tuning(KEY_SKIP_PR, skip)
+        rc, st = s.bdf2_step(5)
+        assert rc == 0
+        counts[skip] = [x["iters"] for x in st]
+        stats[skip] = st
+        states[skip], _ = s.get_state()
+        s.close()
+    say(storage, shape, "last lift sweep without P r: counts", counts[1], "with P r:", counts[0])
+    assert counts[0] == counts[1]
+    assert counts[1][0] > 4 + 8  # the first step outran two predictions
+    for a, b in zip(stats[0], stats[1]):
+        assert a["R_final"] == b["R_final"] and a["R_first"] == b["R_first"]
+    assert np.array_equal(states[0], states[1])
