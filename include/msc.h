@@ -334,9 +334,10 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
  * AA pattern (pairs of steps on one population array; periodic boundaries
  * with FP64 or FP32 storage; 0/1, default 1), 11 = D3Q19 with N_z = 128: run
  * the dual-time sweeps after the first of a step on 4 x 128 tiles of 512
- * threads (0/1, default 1), 12 = 3D with the shadow corrector and FP64 or
- * FP32 storage: the lift sweep enqueued as the last of its step (the step is
- * predicted to accept there) leaves out the residual moments P r, which are
+ * threads (0/1, default 1), 12 = with the shadow corrector and FP64 or FP32
+ * storage, in 3D and in 2D where the row transforms run as passes of their
+ * own (N_y above 256): the lift sweep enqueued as the last of its step (the
+ * step is predicted to accept there) leaves out the residual moments P r, which are
  * formed afterwards from that sweep's input and output only if the step goes
  * on (0/1, default 1).  Results do not depend on these beyond rounding order
  * (keys 6 = 1 and 2 give identical results; keys 10, 11 and 12 give identical

@@ -294,8 +294,9 @@ msc_status msc_kernel_time(msc_ctx* c, int32_t kind, double* seconds, int64_t* l
 // 7 / 8 = pencils / columns per block of the 3D transform passes, 9 = the
 // full-symbol column pass split in three kernels (0 auto / 1 split / 2 fused),
 // 10 = the in-place (AA) explicit march, 11 = the 512-thread D3Q19 dual-time
-// tile at N_z = 128, 12 = the last lift sweep enqueued for a 3D step leaving
-// P r out (formed afterwards only if the step goes on).
+// tile at N_z = 128, 12 = the last lift sweep enqueued for a step leaving P r
+// out (3D, and 2D with row passes of their own; formed afterwards only if the
+// step goes on).
 // Keys 0, 1 and 5-8 re-pick the launch shapes at once; the others apply
 // from the next call.
 msc_status msc_set_tuning(msc_ctx* c, int32_t key, int32_t value) {

@@ -93,6 +93,7 @@ template <class CT, class TM>
 struct Fft2Args {
   CorrGuard g;
   int do_accept;  // Algorithm 1 mode: the first pass decides acceptance (and reconstructs m^{n+1})
+  int decide_only;  // with do_accept: take the decision only (the sweep left P r out)
   int decide;     // the row pass ran inside the sweep: the column pass decides instead
   int adjoint;    // apply chi H^{-H} (transpose of the correction) instead of chi H^{-1}
   int Nx, Ny, lgx, lgy;
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(256) void k_fft2_rows_fwd(Fft2Args<CT, TM> A, Accep
       }
       return;
     }
+    if (A.decide_only) return;
   } else if (A.g.skip()) {
     return;
   }

@@ -40,7 +40,8 @@ struct Tuning {
   int explicit_aa = 1;       // explicit march in place by the AA pattern where available
   int wide_dual = 1;         // D3Q19 at N_z = 128: the 4 x 128 tile of 512 threads for the
                              // dual-time sweeps after the first of a step
-  int skip_pr = 1;           // 3D: the lift sweep enqueued last for a step leaves P r out
+  int skip_pr = 1;           // the lift sweep enqueued last for a step leaves P r out (3D;
+                             // 2D with the row transforms as passes of their own)
 };
 
 class SolverBase {

@@ -1125,11 +1125,13 @@ class Solver : public SolverBase {
   bool corrector_supported() const { return fft_fits(); }
 
   bool fullsym() const { return P.corrector == MSC_CORRECTOR_FULL_SYMBOL; }
-  // 3D shadow corrector with FP64 or FP32 populations: the lift sweep
-  // enqueued as the last of its step leaves P r out (the step is predicted to
-  // accept there); k_recompute_pr forms it if the step goes on
+  // Shadow corrector with FP64 or FP32 populations, 3D or 2D with the row
+  // transforms as passes of their own: the lift sweep enqueued as the last of
+  // its step leaves P r out (the step is predicted to accept there);
+  // k_recompute_pr forms it if the step goes on
   bool skip_pr_ok() const {
-    return D == 3 && tune.skip_pr != 0 && P.corrector == MSC_CORRECTOR_SHADOW && !PopDev<T>::value;
+    return tune.skip_pr != 0 && P.corrector == MSC_CORRECTOR_SHADOW && !PopDev<T>::value &&
+           (D == 3 || !fuse_rows);
   }
   bool wallkin() const { return P.corrector == MSC_CORRECTOR_WALL_KINETIC; }
   bool walls() const { return P.boundary == MSC_BOUNDARY_CAVITY; }
@@ -2197,6 +2199,7 @@ class Solver : public SolverBase {
       Fft2Args<CX, TX> F{};
       F.g = CorrGuard{c, n, ell};
       F.do_accept = Ac ? 1 : 0;
+      F.decide_only = (Ac && decide_only) ? 1 : 0;
       F.adjoint = adjoint ? 1 : 0;
       F.Nx = G.N0;
       F.Ny = G.N2;

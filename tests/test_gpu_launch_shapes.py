@@ -338,3 +338,34 @@ def test_last_lift_sweep_without_pr(M, orc, storage, shape):
     for a, b in zip(stats[0], stats[1]):
         assert a["R_final"] == b["R_final"] and a["R_first"] == b["R_first"]
     assert np.array_equal(states[0], states[1])
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_last_lift_sweep_without_pr_2d(M, orc, storage):
+    """2D at N_y = 512, Re = 100 (the row transforms run as passes of their
+    own; the forward row pass takes the decision): the last lift sweep enqueued for a
+    step leaving P r out (key 12 = 1) and P r always stored (key 12 = 0) give
+    the same counts, the same residuals and bit-identical states over a
+    free-running march whose first step outruns its prediction."""
+    N = 512
+    # Re = 100: the first step needs 10 (FP32) to 17 (FP64) sweeps against a
+    # prediction of 4
+    p0, u0 = W.random_field_2d(N, 100.0 * NU / N, seed=3)
+    states, counts, stats = {}, {}, {}
+    for skip in (0, 1):
+        p = M.make_params(2, N, dt=256.0, eps=1e-10 if storage == "fp64" else 1e-8, storage=storage, n_min=2,
+                          extrap_states=2)
+        s = M.Solver(p, p0, u0)
+        s.set_tuning(KEY_SKIP_PR, skip)
+        rc, st = s.bdf2_step(5)
+        assert rc == 0
+        counts[skip] = [x["iters"] for x in st]
+        stats[skip] = st
+        states[skip], _ = s.get_state()
+        s.close()
+    say(storage, "2D last lift sweep without P r: counts", counts[1], "with P r:", counts[0])
+    assert counts[0] == counts[1]
+    assert counts[1][0] > 4  # the first step outran its prediction
+    for a, b in zip(stats[0], stats[1]):
+        assert a["R_final"] == b["R_final"] and a["R_first"] == b["R_first"]
+    assert np.array_equal(states[0], states[1])
