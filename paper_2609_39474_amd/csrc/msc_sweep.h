@@ -682,6 +682,14 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
   const int tid = threadIdx.x;
 
   CT fprev[SPT][Q], fcur[SPT][Q];
+  // The D3Q19 first sweep with the halo prefetch (one wave per SIMD) keeps
+  // the destination plane's trial values, which every thread holds for a
+  // whole plane step, in LDS instead of registers (each thread reads and
+  // writes only its own entries): FP64 446 -> 370 registers, fewer moves
+  // through the accumulation registers; N = 128 FP64 march 0.703 -> 0.689 ms
+  // per step
+  constexpr bool FPLDS = setup_halo_prefetch<L, T, MODE>() && SPT == 1;
+  __shared__ CT fpl[FPLDS ? Q * NT : 1];
   // deviation storage: the trial's moments at the owned sites, for P r
   constexpr int NMT = (PopDev<T>::value && MODE != SW_EXPLICIT) ? D + 1 : 1;
   double mprev[SPT][NMT], mcur[SPT][NMT];
@@ -964,7 +972,7 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
           const CT v = vv[k];
           if constexpr (!PopDev<T>::value) __builtin_nontemporal_store((T)v, &dst[k * NS + site]);
           if (MODE != SW_EXPLICIT) {
-            const CT r = v - fprev[j][k];
+            const CT r = v - (FPLDS ? fpl[k * NT + tid] : fprev[j][k]);
             if (A.rout) __builtin_nontemporal_store((TM)r, &A.rout[k * NS + site]);
             pr[0] += r;
 #pragma unroll
@@ -1017,7 +1025,12 @@ __global__ __launch_bounds__(NT, (sweep_min_waves<L, T, MODE, T1>())) void k_swe
 #pragma unroll
     for (int j = 0; j < SPT; ++j) {
 #pragma unroll
-      for (int k = 0; k < Q; ++k) fprev[j][k] = fcur[j][k];
+      for (int k = 0; k < Q; ++k) {
+        if constexpr (FPLDS)
+          fpl[k * NT + tid] = fcur[j][k];
+        else
+          fprev[j][k] = fcur[j][k];
+      }
 #pragma unroll
       for (int b = 0; b < NMT; ++b) mprev[j][b] = mcur[j][b];
       c0prev[j] = c0c[j];
