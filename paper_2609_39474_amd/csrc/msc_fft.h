@@ -7,8 +7,9 @@
 // j = 0..N/4 (the negative half follows by conjugate symmetry) and the other
 // axes keep |j| <= N/4.
 //
-// Transforms are radix-4 Stockham passes (one radix-2 pass when log2 N is
-// odd) on complex lines held in LDS, ping-ponging between two LDS arrays; the
+// Transforms are Stockham passes of radix 8 (then one of radix 4 or 2 for the
+// remaining factors of two) on complex lines held in LDS, ping-ponging between
+// two LDS arrays; the
 // twiddle table exp(-2 pi i t/N) is precomputed per axis.  The per-wavevector
 // 3x3 (2D) / 4x4 (3D) solve of Eq. (schur) runs in FP64 inside the kernel that
 // holds the full spectrum line of the last axis.
